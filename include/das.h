@@ -1,0 +1,182 @@
+/*
+ * das.h -- C ABI of the MI355X (gfx950) 3D delay-and-sum library.
+ *
+ * The operator (paper, Sec. 2):
+ *   Eq. (1)  tau_qmn = tau_tx_qn + |p_n - r_m| / c0, with the transmit term of
+ *            the footnote to Eq. (1) (plane wave, diverging wave, or none);
+ *   weight   w_qmn = w_tx_qn * w_rx_mn (paragraph after Eq. (1));
+ *   Eq. (2)  x_bn = sum_q sum_m w_qmn y_bqm[tau_qmn], linear interpolation
+ *            between samples k = floor(f) and k+1 (sentence after Eq. (2)),
+ *   with channel data batched as y[B][Q][M][K] (Sec. 2, last paragraphs).
+ * The readings this library takes where the paper is silent:
+ *   - fractional sample index f = ((D_tx + D_rx)/c - t0) * fs, with
+ *     D_rx = |p - r_m| and D_tx = u.p - L (plane wave along unit u),
+ *     |p - v| - L (diverging wave from virtual source v) or -L (none);
+ *     sample k (0-based) is taken at time t0 + k/fs;
+ *   - taps outside [0, K) read zero;
+ *   - receive weight: uniform, or Hann with f-number F:
+ *     with d = p - r_m, z = d.n_m, rho = |d - z n_m|, a = z/(2F):
+ *     w_rx = (1 + cos(pi rho/a))/2 if z > 0 and rho < a, else 0;
+ *   - voxel n = ix + Nx*(iy + Ny*iz) at origin + (ix, iy, iz) * spacing.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns das_status (DAS_OK = 0).  No exception crosses the
+ *     ABI.  das_last_error() gives a thread-local message for the last failure
+ *     of the calling thread.
+ *   - Arguments are validated on the host before any HIP call; an invalid
+ *     argument returns DAS_ERR_INVALID_ARG and touches no device state.
+ *   - Large buffers (y, ws, x, gx, gy, w_tx, dLdc, f_out) are caller-owned,
+ *     contiguous device memory of the stated layout.  The plan owns only its
+ *     small geometry buffers (allocated by das_plan_create, freed by
+ *     das_plan_destroy).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *     enqueued asynchronously on it; no call synchronizes implicitly, except
+ *     das_plan_create / das_plan_destroy / das_autotune which may.
+ *   - Non-finite inputs propagate unchecked.
+ *   - A plan is not safe to mutate from several threads; enqueuing work from
+ *     one thread per stream on a plan that is not being mutated is safe.
+ */
+#ifndef DAS_MI355X_H
+#define DAS_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DAS_OK = 0,
+  DAS_ERR_INVALID_ARG = -1,   /* bad pointer, size, enum, or geometry */
+  DAS_ERR_UNSUPPORTED = -2,   /* valid, but this algorithm cannot run it */
+  DAS_ERR_HIP = -3,           /* a HIP runtime call failed (see das_last_error) */
+  DAS_ERR_OOM = -4            /* device allocation failed */
+} das_status;
+
+typedef enum { DAS_TX_NONE = 0, DAS_TX_PLANE = 1, DAS_TX_DIVERGING = 2 } das_tx_kind;
+typedef enum { DAS_STORE_F32 = 0, DAS_STORE_F16 = 1, DAS_STORE_BF16 = 2 } das_storage;
+typedef enum { DAS_APOD_UNIFORM = 0, DAS_APOD_HANN_FNUM = 1 } das_apod;
+typedef enum {
+  DAS_ALGO_AUTO = 0,    /* tuned / heuristic choice among the three below */
+  DAS_ALGO_PLAIN = 1,   /* one voxel per lane, direct gathers from y[B][Q][M][K] f32 */
+  DAS_ALGO_TILED = 2,   /* voxel tiles, LDS sample windows, aperture culling */
+  DAS_ALGO_MFMA = 3     /* windowed tile contraction on matrix cores (f16/bf16, B >= 16) */
+} das_algo;
+
+/* One transmit (observation) q: footnote to Eq. (1). */
+typedef struct {
+  int32_t kind;          /* das_tx_kind */
+  double vec[3];         /* PLANE: unit propagation direction u (into the medium);
+                            DIVERGING: virtual source position v (m); NONE: unused */
+  double path_offset;    /* L_q (m), subtracted from the transmit path */
+} das_tx;
+
+/* Voxel grid (Sec. 2): p = origin + (ix, iy, iz) * spacing. */
+typedef struct {
+  double origin[3];      /* m */
+  double spacing[3];     /* m, each > 0 */
+  int32_t dims[3];       /* Nx, Ny, Nz, each >= 1 */
+} das_grid;
+
+typedef struct {
+  int32_t num_elements;        /* M >= 1 */
+  const double* element_pos;   /* host [M][3] (m); copied at plan creation */
+  const double* element_normal;/* host [M][3] or NULL (= +z); normalized on copy */
+  int32_t num_tx;              /* Q >= 1 */
+  const das_tx* tx;            /* host [Q]; copied */
+  das_grid grid;
+  int32_t num_samples;         /* K >= 2 */
+  int32_t max_batch;           /* B upper bound >= 1 */
+  double sound_speed;          /* c0 (m/s) > 0 */
+  double fs;                   /* sampling rate (Hz) > 0 */
+  double t0;                   /* time of sample 0 (s) */
+  int32_t apod;                /* das_apod */
+  double f_number;             /* F > 0 (HANN_FNUM only) */
+  int32_t storage;             /* das_storage of the prepared workspace */
+  int32_t algo;                /* das_algo */
+} das_config;
+
+typedef struct das_plan_s* das_plan;
+
+/* Create a plan on HIP device `hip_device`: validate cfg, copy the geometry
+ * (FP64) to the device.  *out is NULL on failure. */
+das_status das_plan_create(das_plan* out, const das_config* cfg, int hip_device);
+/* Free the plan's device buffers (synchronizes the device).  NULL is a no-op. */
+das_status das_plan_destroy(das_plan p);
+
+/* Replace c0 (m/s, > 0); read by the next enqueued call. */
+das_status das_plan_set_sound_speed(das_plan p, double c);
+/* Optional transmit weights w_tx[Q][N] f32 (device, caller-owned, must outlive
+ * the calls that use it); NULL restores w_tx = 1. */
+das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
+/* Force an algorithm (das_algo) for subsequent calls; AUTO restores the
+ * plan's heuristic / tuned choice. */
+das_status das_plan_set_algo(das_plan p, int32_t algo);
+/* The algorithm das_forward would use for `batch` items. */
+das_status das_plan_get_algo(das_plan p, int32_t batch, int32_t* algo);
+
+/* Size in bytes of the prepared workspace for `batch` items. */
+das_status das_workspace_bytes(das_plan p, int32_t batch, size_t* bytes);
+
+/* Reorder + convert (Sec. 3.2 batch-inner layout, fused with the Sec. 3.3
+ * precision conversion).  y: device [nb][Q][M][K] f32, items b0 .. b0+nb-1 of
+ * a batch of batch_total.  ws: device workspace of das_workspace_bytes(
+ * batch_total) bytes.  Layout written:
+ *   PLAIN:        [batch_total][Q][M][K] f32 (a copy; y itself may be passed
+ *                 as ws to das_forward instead)
+ *   TILED, MFMA:  [Q][M][K][batch_total] in the plan's storage type, rounded
+ *                 to nearest even. */
+das_status das_prepare(das_plan p, const float* y, int32_t b0, int32_t nb, int32_t batch_total,
+                       void* ws, void* stream);
+
+/* Forward, Eq. (2).  ws: prepared workspace for `batch` items.
+ * x: device [batch][N] f32, overwritten. */
+das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void* stream);
+
+/* Adjoint (exact transpose of das_forward as a map y -> x):
+ * gy[b][q][m][j] = sum_n w_qmn ((1-a)[j = k] + a [j = k+1]) gx[b][n].
+ * gx: device [batch][N] f32; gy: device [batch][Q][M][K] f32, overwritten. */
+das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, void* stream);
+
+/* dL/dc = sum_{b,n} gx[b][n] dx[b][n]/dc, with dx/dc = sum_{q,m} w (s(k+1)-s(k)) df/dc,
+ * df/dc = -fs (D_tx + D_rx)/c^2 (right-hand slope at integer f).
+ * y: device [batch][Q][M][K] f32 (caller layout); gx: device [batch][N] f32;
+ * dLdc: device scalar f32, overwritten. */
+das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int32_t batch,
+                                float* dLdc, void* stream);
+
+/* Several forward passes in one persistent launch: for i < count, plan
+ * plans[i] beamforms its prepared workspace ws[i] (batch[i] items) into x[i]
+ * ([batch[i]][N_i] f32).  All plans must live on the same device and use the
+ * TILED layout; their storage types may differ. */
+das_status das_forward_batched(int32_t count, const das_plan* plans, const void* const* ws,
+                               const int32_t* batch, float* const* x, void* stream);
+
+/* Time the candidate tile shapes of the TILED algorithm for `batch` items on
+ * `stream` (using scratch buffers it allocates and frees) and keep the fastest
+ * for this plan.  Synchronizes the stream. */
+das_status das_autotune(das_plan p, int32_t batch, void* stream);
+/* Tile shape index the plan uses for TILED (see das_tile_shape). */
+das_status das_plan_get_tile(das_plan p, int32_t* tile_index);
+das_status das_plan_set_tile(das_plan p, int32_t tile_index);
+/* Dimensions of candidate tile `tile_index` (0 .. das_num_tile_shapes()-1). */
+int32_t das_num_tile_shapes(void);
+das_status das_tile_shape(int32_t tile_index, int32_t dims[3]);
+
+/* Fractional sample indices f as the forward kernels form them (integer part
+ * plus the FP32 tile-relative part, converted exactly to f64), for transmit q,
+ * elements [m0, m1) and voxels [n0, n1).  f_out: device [m1-m0][n1-n0] f64.
+ * Exposes the in-kernel delay formation to the delay-error test. */
+das_status das_debug_delays(das_plan p, int32_t q, int32_t m0, int32_t m1, int32_t n0, int32_t n1,
+                            double* f_out, void* stream);
+
+const char* das_status_string(das_status st);
+const char* das_last_error(void);
+/* Library version string. */
+const char* das_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DAS_MI355X_H */

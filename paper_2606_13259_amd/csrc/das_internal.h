@@ -1,0 +1,66 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer of the
+// delay-and-sum library (gfx950).  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "das.h"
+
+namespace dasmi {
+
+// Device view of a plan's geometry; passed to kernels by value.
+struct Geom {
+  const double* elem;    // [M][3] element positions (m)
+  const float* enorm;    // [M][3] unit element normals, or nullptr (= +z)
+  const double* txvec;   // [Q][3] plane-wave direction or virtual source
+  const double* txoff;   // [Q] path offsets L_q (m)
+  const int* txkind;     // [Q] das_tx_kind
+  const float* w_tx;     // [Q][N] transmit weights or nullptr (= 1)
+  double o[3];           // grid origin (m)
+  double s[3];           // grid spacing (m)
+  int n[3];              // grid dims
+  int M, Q, K;
+  double c;              // sound speed (m/s)
+  double fs;             // sampling rate (Hz)
+  double fsc;            // fs / c   (samples per metre of path)
+  double t0fs;           // t0 * fs  (samples)
+  int apod;              // das_apod
+  float fourF2;          // 4 F^2 (Hann f-number aperture test)
+};
+
+// Voxel tile handled by one workgroup of the windowed kernels.
+struct TileShape {
+  int tx, ty, tz;        // voxels per tile along x, y, z (tx*ty*tz == 256)
+  int lx, lxy;           // log2(tx), log2(tx*ty)
+};
+
+// Window geometry of the windowed kernels for one launch (depends on c).
+struct Window {
+  int dint;              // offset of the tile reference sample inside a window
+  int pairs;             // sample pairs per (transmit, element) window
+};
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (each returns the hipError_t of its launch).
+// ---------------------------------------------------------------------------
+hipError_t launch_reorder(const Geom& g, int storage, const float* y, int b0, int nb, int btot,
+                          void* ws, hipStream_t st);
+hipError_t launch_plain_forward(const Geom& g, const float* y, int B, float* x, hipStream_t st);
+hipError_t launch_tiled_forward(const Geom& g, int storage, const TileShape& ts, const Window& w,
+                                const void* ws, int B, float* x, hipStream_t st);
+hipError_t launch_adjoint(const Geom& g, const TileShape& ts, const Window& w, const float* gx,
+                          int B, float* gy, hipStream_t st);
+hipError_t launch_grad_c(const Geom& g, const float* y, const float* gx, int B, float* dLdc,
+                         hipStream_t st);
+hipError_t launch_debug_delays(const Geom& g, const TileShape& ts, int q, int m0, int m1, int n0,
+                               int n1, double* f_out, hipStream_t st);
+hipError_t launch_mfma_forward(const Geom& g, int storage, const Window& w, const void* ws, int B,
+                               float* x, hipStream_t st);
+
+// LDS bytes the tiled forward kernel needs (0 if it cannot run this shape).
+size_t tiled_lds_bytes(const Geom& g, int storage, int bt, const Window& w);
+int tiled_batch_per_thread(int storage, int B);
+size_t mfma_lds_bytes(const Geom& g, const Window& w);
+
+}  // namespace dasmi

@@ -1,0 +1,305 @@
+// Adjoint (scatter) and sound-speed gradient kernels, plus the delay export
+// used by the delay-error test.
+//
+// Adjoint.  The forward map y -> x of Eq. (2) is linear; its transpose sends
+// each output gradient gx[b][n] back to the two taps each (q, m) term read:
+//   gy[b][q][m][k]   += w (1 - alpha) gx[b][n]
+//   gy[b][q][m][k+1] += w alpha gx[b][n]      (taps inside [0, K) only).
+// One workgroup owns a 256-voxel tile (the same tiles, culling and
+// tile-relative delays as the windowed forward kernel).  For each chunk of
+// elements it accumulates the tile's contributions in LDS windows of
+// (transmit, element) channels with LDS float atomics, then flushes every
+// nonzero window entry to global memory with one float atomic.  Neighbouring
+// voxels hit the same taps, so most of the scatter traffic stays in LDS.
+// The order of the float atomics is not fixed: results are reproducible to
+// FP32 rounding, not bit for bit.
+//
+// Sound-speed gradient.  x depends on c only through f:
+//   dx/dc = sum_{q,m} w (s(k+1) - s(k)) df/dc,  df/dc = -(f + t0 fs) / c,
+// (right-hand slope at integer f).  The kernel gathers like the plain forward
+// kernel and reduces sum_{b,n} gx[b][n] dx[b][n]/dc to one scalar.
+#include "das_device.h"
+
+namespace dasmi {
+namespace {
+
+constexpr int QG = 16;
+constexpr int NT = 256;
+constexpr int MCA = 8;  // elements per adjoint chunk
+
+__global__ void fill_zero(float* __restrict__ p, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.f;
+}
+
+hipError_t zero(float* p, size_t n, hipStream_t st) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(fill_zero, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+struct AInfo {
+  float ex, ey, ez, en, h;
+  int krx, m, pad;
+};
+
+__global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Window win,
+                                                      const float* __restrict__ gx, int B,
+                                                      float* __restrict__ gy, int ntx, int nty,
+                                                      int ntiles, int per_xcd) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int P = win.pairs + 1;  // window samples
+  float* accw = reinterpret_cast<float*>(smem);                       // [QG][MCA][P]
+  AInfo* minfo = reinterpret_cast<AInfo*>(accw + QG * MCA * P);        // [MCA]
+  int* ktxs = reinterpret_cast<int*>(minfo + MCA);                      // [QG]
+  int* wcount = ktxs + QG;                                              // [4]
+  uint16_t* act = reinterpret_cast<uint16_t*>(wcount + 4);              // [M]
+
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (tile >= ntiles) return;
+  const int b = blockIdx.y;
+  const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = tile / (ntx * nty);
+  const int lx = t & (ts.tx - 1), ly = (t >> ts.lx) & (ts.ty - 1), lz = t >> ts.lxy;
+  const int ix = tix * ts.tx + lx, iy = tiy * ts.ty + ly, iz = tiz * ts.tz + lz;
+  const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+  const int K = g.K, M = g.M;
+
+  const float hx = 0.5f * (ts.tx - 1), hy = 0.5f * (ts.ty - 1), hz = 0.5f * (ts.tz - 1);
+  double px, py, pz;
+  tile_ref_point(g, tix * ts.tx + (double)hx, tiy * ts.ty + (double)hy, tiz * ts.tz + (double)hz,
+                 px, py, pz);
+  const float dx = ((float)lx - hx) * (float)g.s[0];
+  const float dy = ((float)ly - hy) * (float)g.s[1];
+  const float dz = ((float)lz - hz) * (float)g.s[2];
+  const float dp2 = dx * dx + dy * dy + dz * dz;
+  const float fscf = (float)g.fsc;
+  const bool inside = in_grid(g, ix, iy, iz);
+  const int n = grid_index(g, ix, iy, iz);
+  const float gv = inside ? gx[(size_t)b * N + n] : 0.f;
+
+  const int nact = cull_elements(g, px, py, pz, hx, hy, hz, wcount, act);
+  // a tile whose upstream gradient is zero everywhere scatters nothing
+  if (__syncthreads_or(gv != 0.f) == 0) return;
+
+  for (int q0 = 0; q0 < g.Q; q0 += QG) {
+    const int qn = min(QG, g.Q - q0);
+    __syncthreads();
+    if (t < qn) ktxs[t] = make_tx_ref(g, q0 + t, px, py, pz).ktx;
+    float bq[QG], wq[QG];
+#pragma unroll
+    for (int q = 0; q < QG; ++q) {
+      bq[q] = 0.f;
+      wq[q] = 0.f;
+      if (q < qn) {
+        const TxRef r = make_tx_ref(g, q0 + q, px, py, pz);
+        bq[q] = fmaf(delta_tx(r, dx, dy, dz, dp2), fscf, r.g);
+        wq[q] = gv * ((g.w_tx && inside) ? g.w_tx[(size_t)(q0 + q) * N + n] : 1.f);
+      }
+    }
+    for (int c0 = 0; c0 < nact; c0 += MCA) {
+      const int mcn = min(MCA, nact - c0);
+      __syncthreads();
+      for (int i = t; i < QG * MCA * P; i += NT) accw[i] = 0.f;
+      if (t < mcn) {
+        const int m = act[c0 + t];
+        const RxRef r = make_rx_ref(g, m, px, py, pz);
+        minfo[t] = AInfo{r.ex, r.ey, r.ez, r.en, r.h, r.krx, m, 0};
+      }
+      __syncthreads();
+      for (int mc = 0; mc < mcn; ++mc) {
+        const AInfo mi = minfo[mc];
+        const float w = rx_weight(g, mi.m, mi.ex + dx, mi.ey + dy, mi.ez + dz);
+        if (__ballot(w != 0.f && gv != 0.f) == 0ull) continue;
+        const float a = fmaf(delta_dist(mi.ex, mi.ey, mi.ez, mi.en, dx, dy, dz, dp2), fscf, mi.h);
+        float* base = accw + mc * P + win.dint;
+#pragma unroll
+        for (int q = 0; q < QG; ++q) {
+          if (q < qn) {
+            const float f = a + bq[q];
+            const float fl = floorf(f);
+            const float al = f - fl;
+            const float c = w * wq[q];
+            if (c != 0.f) {
+              float* p = base + q * MCA * P + (int)fl;
+              atomicAdd(p, c - c * al);
+              atomicAdd(p + 1, c * al);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // flush: wave w flushes windows w, w+4, ...
+      for (int wi = wave; wi < QG * MCA; wi += 4) {
+        const int q = wi / MCA, mc = wi % MCA;
+        if (q >= qn || mc >= mcn) continue;
+        const int j0 = ktxs[q] + minfo[mc].krx - win.dint;
+        float* dst = gy + (((size_t)b * g.Q + q0 + q) * M + minfo[mc].m) * (size_t)K;
+        const float* src = accw + (q * MCA + mc) * P;
+        for (int p = lane; p < P; p += 64) {
+          const float v = src[p];
+          const int j = j0 + p;
+          if (v != 0.f && j >= 0 && j < K) atomicAdd(dst + j, v);
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+
+template <int BT>
+__global__ __launch_bounds__(256) void grad_c_gather(Geom g, const float* __restrict__ y,
+                                                     const float* __restrict__ gx, int B,
+                                                     float* __restrict__ out, int nbx, int nby,
+                                                     int nblocks, float inv_c) {
+  __shared__ float red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int blk = blockIdx.x * 4 + wave;
+  const int b0 = blockIdx.y * BT;
+  float total = 0.f;
+  if (blk < nblocks) {
+    const int bxi = blk % nbx, byi = (blk / nbx) % nby, bzi = blk / (nbx * nby);
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const int ix = bxi * 4 + lx, iy = byi * 4 + ly, iz = bzi * 4 + lz;
+    double px, py, pz;
+    tile_ref_point(g, bxi * 4 + 1.5, byi * 4 + 1.5, bzi * 4 + 1.5, px, py, pz);
+    const float dx = (float)(lx - 1.5f) * (float)g.s[0];
+    const float dy = (float)(ly - 1.5f) * (float)g.s[1];
+    const float dz = (float)(lz - 1.5f) * (float)g.s[2];
+    const float dp2 = dx * dx + dy * dy + dz * dz;
+    const float fscf = (float)g.fsc;
+    const float t0fs = (float)g.t0fs;
+    const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    const bool inside = in_grid(g, ix, iy, iz);
+    const int n = grid_index(g, ix, iy, iz);
+    const size_t MK = (size_t)g.M * g.K, QMK = (size_t)g.Q * MK;
+    float gxv[BT];
+#pragma unroll
+    for (int b = 0; b < BT; ++b) gxv[b] = (inside && b0 + b < B) ? gx[(size_t)(b0 + b) * N + n] : 0.f;
+    for (int q = 0; q < g.Q; ++q) {
+      const TxRef tr = make_tx_ref(g, q, px, py, pz);
+      const float bq = fmaf(delta_tx(tr, dx, dy, dz, dp2), fscf, tr.g);
+      const float wt = (g.w_tx && inside) ? g.w_tx[(size_t)q * N + n] : 1.f;
+      for (int m0 = 0; m0 < g.M; m0 += 64) {
+        RxRef mine = {};
+        if (m0 + lane < g.M) mine = make_rx_ref(g, m0 + lane, px, py, pz);
+        const int mn = min(64, g.M - m0);
+        for (int mm = 0; mm < mn; ++mm) {
+          const int m = m0 + mm;
+          const float ex = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.ex), mm));
+          const float ey = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.ey), mm));
+          const float ez = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.ez), mm));
+          const float en = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.en), mm));
+          const float h = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.h), mm));
+          const int krx = __builtin_amdgcn_readlane(mine.krx, mm);
+          const float w = wt * rx_weight(g, m, ex + dx, ey + dy, ez + dz);
+          if (w == 0.f) continue;
+          const float f = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, h) + bq;
+          const float fl = floorf(f);
+          const int kb = tr.ktx + krx;
+          const int k = (int)fl + kb;
+          // f + t0 fs in samples, formed in FP32 from its integer and local parts
+          const float fabs_ = (float)kb + f + t0fs;
+          const float dfdc = -fabs_ * inv_c;
+          const float* yq = y + (size_t)q * MK + (size_t)m * g.K;
+#pragma unroll
+          for (int b = 0; b < BT; ++b) {
+            if (b0 + b < B) {
+              const float* yb = yq + (size_t)(b0 + b) * QMK;
+              const float s1 = (k >= 0 && k < g.K) ? yb[k] : 0.f;
+              const float s2 = (k + 1 >= 0 && k + 1 < g.K) ? yb[k + 1] : 0.f;
+              total = fmaf(gxv[b] * w * dfdc, s2 - s1, total);
+            }
+          }
+        }
+      }
+    }
+  }
+  // wave + block reduction, one atomic per block
+  for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off);
+  if (lane == 0) red[wave] = total;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, red[0] + red[1] + red[2] + red[3]);
+}
+
+// ----------------------------------------------------------------------------
+
+__global__ void debug_delays(Geom g, TileShape ts, int q, int m0, int m1, int n0, int n1,
+                             double* __restrict__ out) {
+  const long long nn = n1 - n0;
+  const long long total = (long long)(m1 - m0) * nn;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int m = m0 + (int)(i / nn);
+  const int n = n0 + (int)(i % nn);
+  const int ix = n % g.n[0], iy = (n / g.n[0]) % g.n[1], iz = n / (g.n[0] * g.n[1]);
+  const int tix = ix / ts.tx, tiy = iy / ts.ty, tiz = iz / ts.tz;
+  const float hx = 0.5f * (ts.tx - 1), hy = 0.5f * (ts.ty - 1), hz = 0.5f * (ts.tz - 1);
+  double px, py, pz;
+  tile_ref_point(g, tix * ts.tx + (double)hx, tiy * ts.ty + (double)hy, tiz * ts.tz + (double)hz,
+                 px, py, pz);
+  const float dx = ((float)(ix - tix * ts.tx) - hx) * (float)g.s[0];
+  const float dy = ((float)(iy - tiy * ts.ty) - hy) * (float)g.s[1];
+  const float dz = ((float)(iz - tiz * ts.tz) - hz) * (float)g.s[2];
+  const float dp2 = dx * dx + dy * dy + dz * dz;
+  const float fscf = (float)g.fsc;
+  const RxRef r = make_rx_ref(g, m, px, py, pz);
+  const TxRef tr = make_tx_ref(g, q, px, py, pz);
+  const float a = fmaf(delta_dist(r.ex, r.ey, r.ez, r.en, dx, dy, dz, dp2), fscf, r.h);
+  const float bq = fmaf(delta_tx(tr, dx, dy, dz, dp2), fscf, tr.g);
+  out[i] = (double)(r.krx + tr.ktx) + (double)(a + bq);
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const Geom& g, const TileShape& ts, const Window& w, const float* gx,
+                          int B, float* gy, hipStream_t st) {
+  hipError_t e = zero(gy, (size_t)B * g.Q * g.M * g.K, st);
+  if (e != hipSuccess) return e;
+  const int ntx = (g.n[0] + ts.tx - 1) / ts.tx, nty = (g.n[1] + ts.ty - 1) / ts.ty,
+            ntz = (g.n[2] + ts.tz - 1) / ts.tz;
+  const int ntiles = ntx * nty * ntz;
+  const int per_xcd = (ntiles + 7) / 8;
+  const int P = w.pairs + 1;
+  size_t lds = (size_t)QG * MCA * P * 4 + MCA * sizeof(AInfo) + QG * 4 + 16 + (size_t)g.M * 2;
+  lds = (lds + 15) & ~(size_t)15;
+  if (lds > 65536) {
+    e = hipFuncSetAttribute((const void*)adjoint_scatter,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(adjoint_scatter, dim3(per_xcd * 8, B), dim3(NT), lds, st, g, ts, w, gx, B, gy,
+                     ntx, nty, ntiles, per_xcd);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_c(const Geom& g, const float* y, const float* gx, int B, float* dLdc,
+                         hipStream_t st) {
+  hipError_t e = zero(dLdc, 1, st);
+  if (e != hipSuccess) return e;
+  const int nbx = (g.n[0] + 3) / 4, nby = (g.n[1] + 3) / 4, nbz = (g.n[2] + 3) / 4;
+  const int nblocks = nbx * nby * nbz;
+  const float inv_c = (float)(1.0 / g.c);
+  if (B >= 4) {
+    hipLaunchKernelGGL(grad_c_gather<4>, dim3((nblocks + 3) / 4, (B + 3) / 4), dim3(256), 0, st, g,
+                       y, gx, B, dLdc, nbx, nby, nblocks, inv_c);
+  } else if (B >= 2) {
+    hipLaunchKernelGGL(grad_c_gather<2>, dim3((nblocks + 3) / 4, (B + 1) / 2), dim3(256), 0, st, g,
+                       y, gx, B, dLdc, nbx, nby, nblocks, inv_c);
+  } else {
+    hipLaunchKernelGGL(grad_c_gather<1>, dim3((nblocks + 3) / 4, B), dim3(256), 0, st, g, y, gx, B,
+                       dLdc, nbx, nby, nblocks, inv_c);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_delays(const Geom& g, const TileShape& ts, int q, int m0, int m1, int n0,
+                               int n1, double* f_out, hipStream_t st) {
+  const long long total = (long long)(m1 - m0) * (n1 - n0);
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  hipLaunchKernelGGL(debug_delays, dim3(blocks), dim3(256), 0, st, g, ts, q, m0, m1, n0, n1, f_out);
+  return hipGetLastError();
+}
+
+}  // namespace dasmi
