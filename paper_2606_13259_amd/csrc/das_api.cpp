@@ -29,9 +29,12 @@ das_status hip_fail(hipError_t e, const char* what) {
   return fail(DAS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// Candidate voxel tiles of the windowed kernels (256 voxels each).
-const int kTiles[][3] = {{8, 8, 4}, {16, 4, 4}, {4, 8, 8}, {16, 8, 2},
-                         {8, 4, 8}, {16, 16, 1}, {32, 8, 1}, {4, 4, 16}};
+// Candidate voxel tiles of the windowed kernels: indices below kFirstBox are
+// 256-voxel workgroup tiles, the others 64-voxel wavefront boxes.
+const int kTiles[][3] = {{8, 8, 4}, {16, 4, 4}, {4, 8, 8}, {16, 8, 2}, {8, 4, 8}, {16, 16, 1},
+                         {32, 8, 1}, {4, 4, 16}, {4, 4, 4}, {8, 4, 2}, {4, 8, 2}, {8, 8, 1},
+                         {16, 4, 1}, {2, 8, 4}, {4, 2, 8}, {2, 4, 8}};
+constexpr int kFirstBox = 8;
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int ilog2(int v) {
@@ -71,6 +74,42 @@ bool finite3(const double* v) {
 }
 
 }  // namespace
+
+namespace dasmi {
+
+int tiled_batch_per_thread(int storage, int B) {
+  (void)storage;
+  if (B >= 4) return 4;
+  if (B >= 2) return 2;
+  return 1;
+}
+
+size_t wave_lds_bytes(const Geom& g, int bt, const Window& w) {
+  const int qn = g.Q == 1 ? 1 : g.Q <= 4 ? 4 : g.Q <= 8 ? 8 : 16;
+  return (size_t)4 * qn * (w.pairs + 1) * bt * 4;
+}
+
+size_t tiled_lds_bytes(const Geom& g, int storage, int bt, const Window& w) {
+  if (storage == DAS_STORE_F32) return tiled_lds_f32(g, bt, w);
+  if (storage == DAS_STORE_F16) return tiled_lds_f16(g, bt, w);
+  return tiled_lds_bf16(g, bt, w);
+}
+
+hipError_t launch_wave_forward(const Geom& g, int storage, const TileShape& ts, const Window& w,
+                               const void* ws, int B, float* x, hipStream_t st) {
+  if (storage == DAS_STORE_F32) return wave_forward_f32(g, ts, w, ws, B, x, st);
+  if (storage == DAS_STORE_F16) return wave_forward_f16(g, ts, w, ws, B, x, st);
+  return wave_forward_bf16(g, ts, w, ws, B, x, st);
+}
+
+hipError_t launch_tiled_forward(const Geom& g, int storage, const TileShape& ts, const Window& w,
+                                const void* ws, int B, float* x, hipStream_t st) {
+  if (storage == DAS_STORE_F32) return tiled_forward_f32(g, ts, w, ws, B, x, st);
+  if (storage == DAS_STORE_F16) return tiled_forward_f16(g, ts, w, ws, B, x, st);
+  return tiled_forward_bf16(g, ts, w, ws, B, x, st);
+}
+
+}  // namespace dasmi
 
 struct das_plan_s {
   int device = 0;
@@ -132,9 +171,19 @@ Window make_window(const das_plan_s* p, const TileShape& ts) {
 bool tiled_fits(const das_plan_s* p, int tile, int B) {
   const Geom g = make_geom(p);
   const Window w = make_window(p, tile_shape(tile));
-  const int st = p->cfg.storage == DAS_STORE_F32 ? DAS_STORE_F32 : DAS_STORE_F16;
-  const size_t lds = tiled_lds_bytes(g, st, tiled_batch_per_thread(st, B), w);
-  return lds > 0 && lds <= kMaxLds && w.pairs < 100000;
+  const int st = p->cfg.storage;
+  const int bt = tiled_batch_per_thread(st, B);
+  const size_t lds = tile >= kFirstBox ? wave_lds_bytes(g, bt, w) : tiled_lds_bytes(g, st, bt, w);
+  // one lane per window sample
+  return lds > 0 && lds <= kMaxLds && w.pairs + 1 <= 64;
+}
+
+hipError_t launch_windowed(const das_plan_s* p, const Geom& g, int tile, const void* ws, int B,
+                           float* x, hipStream_t st) {
+  const TileShape ts = tile_shape(tile);
+  const Window w = make_window(p, ts);
+  if (tile >= kFirstBox) return launch_wave_forward(g, p->cfg.storage, ts, w, ws, B, x, st);
+  return launch_tiled_forward(g, p->cfg.storage, ts, w, ws, B, x, st);
 }
 
 int choose_algo(const das_plan_s* p, int B) {
@@ -393,8 +442,7 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
   } else if (algo == DAS_ALGO_TILED) {
     if (!tiled_fits(p, p->tile, batch))
       return fail(DAS_ERR_UNSUPPORTED, "tile windows do not fit in LDS for this geometry");
-    const TileShape ts = tile_shape(p->tile);
-    e = launch_tiled_forward(g, p->cfg.storage, ts, make_window(p, ts), ws, batch, x, st);
+    e = launch_windowed(p, g, p->tile, ws, batch, x, st);
   } else {
     return fail(DAS_ERR_UNSUPPORTED, "MFMA form not available in this build");
   }
@@ -460,12 +508,9 @@ das_status das_autotune(das_plan p, int32_t batch, void* stream) {
   const Geom g = make_geom(p);
   for (int ti = 0; ti < kNumTiles && e == hipSuccess; ++ti) {
     if (!tiled_fits(p, ti, batch)) continue;
-    const TileShape ts = tile_shape(ti);
-    const Window w = make_window(p, ts);
-    e = launch_tiled_forward(g, p->cfg.storage, ts, w, ws, batch, x, st);  // warm-up
+    e = launch_windowed(p, g, ti, ws, batch, x, st);  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, st);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r)
-      e = launch_tiled_forward(g, p->cfg.storage, ts, w, ws, batch, x, st);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_windowed(p, g, ti, ws, batch, x, st);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;

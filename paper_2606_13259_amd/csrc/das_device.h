@@ -120,7 +120,7 @@ __device__ inline float hann_fnum(float dx, float dy, float dz, float nx, float 
   const float zz = z * z;
   const float t4 = rho2 * fourF2;
   if (!(z > 0.f) || !(t4 < zz)) return 0.f;
-  const float t = t4 / zz;
+  const float t = t4 * __builtin_amdgcn_rcpf(zz);
   const float u = -2.4674011002723395f * t;  // -(pi^2 / 4) t
   float c = 1.1470745597729725e-11f;          // 1/14!
   c = fmaf(c, u, 2.08767569878681e-09f);      // 1/12!

@@ -58,6 +58,27 @@ hipError_t launch_debug_delays(const Geom& g, const TileShape& ts, int q, int m0
 hipError_t launch_mfma_forward(const Geom& g, int storage, const Window& w, const void* ws, int B,
                                float* x, hipStream_t st);
 
+// Windowed forward, one instantiation set per storage type.
+hipError_t tiled_forward_f32(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
+                             int B, float* x, hipStream_t st);
+hipError_t tiled_forward_f16(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
+                             int B, float* x, hipStream_t st);
+hipError_t tiled_forward_bf16(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
+                              int B, float* x, hipStream_t st);
+hipError_t wave_forward_f32(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
+                           int B, float* x, hipStream_t st);
+hipError_t wave_forward_f16(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
+                           int B, float* x, hipStream_t st);
+hipError_t wave_forward_bf16(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
+                            int B, float* x, hipStream_t st);
+size_t tiled_lds_f32(const Geom& g, int bt, const Window& w);
+size_t tiled_lds_f16(const Geom& g, int bt, const Window& w);
+size_t tiled_lds_bf16(const Geom& g, int bt, const Window& w);
+
+hipError_t launch_wave_forward(const Geom& g, int storage, const TileShape& ts, const Window& w,
+                               const void* ws, int B, float* x, hipStream_t st);
+size_t wave_lds_bytes(const Geom& g, int bt, const Window& w);
+
 // LDS bytes the tiled forward kernel needs (0 if it cannot run this shape).
 size_t tiled_lds_bytes(const Geom& g, int storage, int bt, const Window& w);
 int tiled_batch_per_thread(int storage, int B);

@@ -1,0 +1,425 @@
+// Windowed forward kernel for the VALU (paper, Sec. 3.2 batch-inner tiling and
+// Sec. 3.3 mixed-precision storage, re-designed for gfx950).
+//
+// Work decomposition.  One 256-lane workgroup owns a voxel tile of 256 voxels
+// (shape tx*ty*tz, one voxel per lane; each 64-lane wavefront owns a box of 64
+// of them) and BT batch items.  Neighbouring voxels need nearby sample indices
+// of every (transmit, element) channel (Sec. 3.1), so for each channel the
+// workgroup stages one contiguous window of samples into LDS with coalesced
+// loads from the batch-inner workspace ws[Q][M][K][B], converted to FP32, and
+// every lane then reads its two taps with one ds_read2_b32.
+//
+//   * Tile set-up: every element is tested against the receive-aperture cone
+//     (a conservative sphere-cone test for the tile and for each wavefront's
+//     box).  The elements that can reach the tile are compacted into an LDS
+//     list with their FP64 reference terms (tile-relative delays, see
+//     das_device.h) and a 4-bit mask of the wavefronts they can reach; a
+//     wavefront skips an element of the list with one bit test.
+//   * Windows: the window of channel (q, m) starts at ktx_q + krx_m - dint,
+//     where ktx_q + krx_m is the integer part of the tile reference index and
+//     dint bounds |f - (ktx + krx)| over the tile (triangle inequality on the
+//     tile half-diagonal).  Taps outside [0, K) are zero-filled while staging.
+//   * Pipelining: element chunks (MC elements x QN transmits) are staged
+//     through registers: the global loads of chunk c+1 are issued before the
+//     interpolation of chunk c and written to LDS after it, so memory latency
+//     hides behind arithmetic.
+//   * Loop order: element chunks outer, transmits inner; the receive geometry
+//     and weight of a (voxel, element) pair are formed once and reused across
+//     the QN transmits of a group, whose QN LDS reads are all issued before
+//     the first is consumed.
+//   * Block ids are remapped so that each XCD (and its L2) receives a
+//     contiguous range of tiles, whose windows overlap.
+//
+// Arithmetic: delays are tile-relative FP32 with FP64 reference terms;
+// samples are converted to FP32 before interpolation; accumulation is FP32.
+// Transmits are processed in groups of QN (compile-time, so the transmit loop
+// unrolls); a group that is not full is padded with zero-filled windows.
+#pragma once
+#include "das_device.h"
+
+namespace dasmi {
+namespace tiled {
+
+constexpr int NT = 256;
+constexpr int EMAX = 512;  // active elements held per pass
+
+template <class T> __device__ inline float to_f32(T v);
+template <> __device__ inline float to_f32<float>(float v) { return v; }
+template <> __device__ inline float to_f32<_Float16>(_Float16 v) { return (float)v; }
+template <> __device__ inline float to_f32<uint16_t>(uint16_t v) {
+  return __uint_as_float(((uint32_t)v) << 16);
+}
+
+// Elements per chunk: QN * MC * BT = 64 windows of at most 64 samples
+// (16 KiB of LDS at most; 16 staging registers per lane).
+template <int BT, int QN>
+constexpr int chunk_elems() {
+  return 64 / (QN * BT) < 1 ? 1 : 64 / (QN * BT);
+}
+
+struct QInfo {  // per transmit of the current group, 32 bytes
+  float vx, vy, vz, vn, g;
+  int ktx, kind, pad;
+};
+
+// LDS layout (bytes), shared by the kernel and the host-side size query.
+struct Layout {
+  int win, ex, ey, ez, eh, ek, em, q, wc, total;
+};
+__host__ __device__ inline Layout layout(int QN, int MC, int BT, int W) {
+  Layout L;
+  L.win = 0;
+  int o = ((QN * MC * W * BT * 4) + 15) & ~15;
+  L.ex = o; o += EMAX * 4;
+  L.ey = o; o += EMAX * 4;
+  L.ez = o; o += EMAX * 4;
+  L.eh = o; o += EMAX * 4;
+  L.ek = o; o += EMAX * 4;
+  L.em = o; o += EMAX * 4;
+  L.q = o; o += 16 * (int)sizeof(QInfo);
+  L.wc = o; o += 16;
+  L.total = o;
+  return L;
+}
+
+// Conservative test: can any point of the sphere (centre c, radius R) lie in
+// the open receive cone of element m (apex r_m, axis n_m, half-angle theta
+// with tan theta = 1/(2F))?  With D = |c - r_m|, cos(phi) = (c - r_m).n / D
+// and beta = asin(R/D), the sphere meets the cone iff phi < theta + beta, i.e.
+// cos(phi) > cos(theta) cos(beta) - sin(theta) sin(beta) (when theta + beta
+// < pi, which holds here since theta < pi/2 and beta <= pi/2).
+__device__ inline bool sphere_meets_cone(float ex, float ey, float ez, float nx, float ny,
+                                         float nz, float R, float cth, float sth) {
+  const float D2 = ex * ex + ey * ey + ez * ez;
+  const float R2 = R * R * 1.0001f + 1e-18f;
+  if (D2 <= R2) return true;
+  const float invD = __builtin_amdgcn_rsqf(D2);
+  const float cphi = (ex * nx + ey * ny + ez * nz) * invD;
+  const float sb = R * invD;
+  const float cb = __builtin_amdgcn_sqrtf(fmaxf(0.f, 1.f - sb * sb));
+  return cphi > cth * cb - sth * sb - 1e-4f;
+}
+
+// Per-thread staging registers for one chunk: lane p of wave w holds sample
+// p of windows w, w+4, ... (BT batch items each).
+template <int BT, int QN, int MC>
+struct Stage {
+  static constexpr int WPW = (QN * MC + 3) / 4;
+  float v[WPW][BT];
+};
+
+template <class T, int BT, int QN, int MC>
+__device__ inline void stage_load(Stage<BT, QN, MC>& st, const T* __restrict__ ws, const int* ktx,
+                                  const int* ek, const int* em, int c0, int q0, int qn, int mcn,
+                                  int M, int K, int B, int b0, int W, int dint, int wave, int lane) {
+  constexpr int WPW = Stage<BT, QN, MC>::WPW;
+#pragma unroll
+  for (int k = 0; k < WPW; ++k) {
+    const int wi = wave + 4 * k;
+    const int q = wi / MC, mc = wi % MC;
+#pragma unroll
+    for (int b = 0; b < BT; ++b) st.v[k][b] = 0.f;
+    if (wi < QN * MC && q < qn && mc < mcn && lane < W) {
+      const int e = c0 + mc;
+      const int j = ktx[q] + ek[e] - dint + lane;
+      if (j >= 0 && j < K) {
+        const T* src = ws + (((size_t)(q0 + q) * M + (em[e] & 0xffff)) * (size_t)K + j) * B + b0;
+#pragma unroll
+        for (int b = 0; b < BT; ++b)
+          if (b0 + b < B) st.v[k][b] = to_f32<T>(src[b]);
+      }
+    }
+  }
+}
+
+template <int BT, int QN, int MC>
+__device__ inline void stage_store(const Stage<BT, QN, MC>& st, float* win, int mcn, int W,
+                                   int wave, int lane) {
+  constexpr int WPW = Stage<BT, QN, MC>::WPW;
+#pragma unroll
+  for (int k = 0; k < WPW; ++k) {
+    const int wi = wave + 4 * k;
+    const int mc = wi % MC;
+    if (wi < QN * MC && mc < mcn && lane < W) {
+      float* dst = win + (wi * W + lane) * BT;
+#pragma unroll
+      for (int b = 0; b < BT; ++b) dst[b] = st.v[k][b];
+    }
+  }
+}
+
+template <class T, int BT, int QN, bool WTX>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void tiled_forward(
+    Geom g, TileShape ts, Window win, const T* __restrict__ ws, int B, float* __restrict__ x,
+    int ntx, int nty, int ntiles, int per_xcd) {
+  constexpr int MC = chunk_elems<BT, QN>();
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int W = win.pairs + 1;  // samples per window
+  const Layout L = layout(QN, MC, BT, W);
+  float* wsm = reinterpret_cast<float*>(smem + L.win);
+  float* eX = reinterpret_cast<float*>(smem + L.ex);
+  float* eY = reinterpret_cast<float*>(smem + L.ey);
+  float* eZ = reinterpret_cast<float*>(smem + L.ez);
+  float* eH = reinterpret_cast<float*>(smem + L.eh);
+  int* eK = reinterpret_cast<int*>(smem + L.ek);
+  int* eM = reinterpret_cast<int*>(smem + L.em);
+  QInfo* qinfo = reinterpret_cast<QInfo*>(smem + L.q);
+  int* wcount = reinterpret_cast<int*>(smem + L.wc);
+  __shared__ int ktx_s[16];
+
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+  const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (tile >= ntiles) return;
+  const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = tile / (ntx * nty);
+  const int lx = t & (ts.tx - 1), ly = (t >> ts.lx) & (ts.ty - 1), lz = t >> ts.lxy;
+  const int ix = tix * ts.tx + lx, iy = tiy * ts.ty + ly, iz = tiz * ts.tz + lz;
+  const int b0 = blockIdx.y * BT;
+  const int K = g.K, M = g.M;
+  const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+
+  const float hx = 0.5f * (ts.tx - 1), hy = 0.5f * (ts.ty - 1), hz = 0.5f * (ts.tz - 1);
+  double px, py, pz;
+  tile_ref_point(g, tix * ts.tx + (double)hx, tiy * ts.ty + (double)hy, tiz * ts.tz + (double)hz,
+                 px, py, pz);
+  const float sx = (float)g.s[0], sy = (float)g.s[1], sz = (float)g.s[2];
+  const float dx = ((float)lx - hx) * sx, dy = ((float)ly - hy) * sy, dz = ((float)lz - hz) * sz;
+  const float dp2 = dx * dx + dy * dy + dz * dz;
+  const float fscf = (float)g.fsc;
+  const bool inside = in_grid(g, ix, iy, iz);
+  const int n = grid_index(g, ix, iy, iz);
+  const uint32_t mybit = 1u << (16 + wave);
+
+  // Bounding spheres (relative to the tile reference) of the tile and of the
+  // four wavefront boxes (64 consecutive lanes form a box of the tile).
+  const float Rt = sqrtf(hx * hx * sx * sx + hy * hy * sy * sy + hz * hz * sz * sz);
+  float wcx[4], wcy[4], wcz[4], wr[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int a = 64 * w, bb = 64 * w + 63;
+    const float ax0 = (float)(a & (ts.tx - 1)), ay0 = (float)((a >> ts.lx) & (ts.ty - 1)),
+                az0 = (float)(a >> ts.lxy);
+    const float ax1 = (float)(bb & (ts.tx - 1)), ay1 = (float)((bb >> ts.lx) & (ts.ty - 1)),
+                az1 = (float)(bb >> ts.lxy);
+    wcx[w] = (0.5f * (ax0 + ax1) - hx) * sx;
+    wcy[w] = (0.5f * (ay0 + ay1) - hy) * sy;
+    wcz[w] = (0.5f * (az0 + az1) - hz) * sz;
+    wr[w] = 0.5f * sqrtf((ax1 - ax0) * (ax1 - ax0) * sx * sx + (ay1 - ay0) * (ay1 - ay0) * sy * sy +
+                         (az1 - az0) * (az1 - az0) * sz * sz);
+  }
+  const bool hann = g.apod == DAS_APOD_HANN_FNUM;
+  const float twoF = sqrtf(g.fourF2);
+  const float cth = hann ? twoF * rsqrtf(1.f + g.fourF2) : -1.f;
+  const float sth = hann ? rsqrtf(1.f + g.fourF2) : 0.f;
+
+  float acc[BT];
+#pragma unroll
+  for (int b = 0; b < BT; ++b) acc[b] = 0.f;
+
+  int mscan = 0;
+  while (mscan < M) {
+    // ---- compact the next batch of elements that can reach this tile ----
+    int nact = 0;
+    __syncthreads();
+    while (mscan < M && nact + NT <= EMAX) {
+      const int m = mscan + t;
+      uint32_t mask = 0;
+      double ex = 0.0, ey = 0.0, ez = 0.0;
+      if (m < M) {
+        ex = px - g.elem[3 * m + 0];
+        ey = py - g.elem[3 * m + 1];
+        ez = pz - g.elem[3 * m + 2];
+        if (!hann) {
+          mask = 0xfu;
+        } else {
+          float nx = 0.f, ny = 0.f, nz = 1.f;
+          if (g.enorm) {
+            nx = g.enorm[3 * m + 0];
+            ny = g.enorm[3 * m + 1];
+            nz = g.enorm[3 * m + 2];
+          }
+          const float fx = (float)ex, fy = (float)ey, fz = (float)ez;
+          if (sphere_meets_cone(fx, fy, fz, nx, ny, nz, Rt, cth, sth)) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+              if (sphere_meets_cone(fx + wcx[w], fy + wcy[w], fz + wcz[w], nx, ny, nz, wr[w], cth, sth))
+                mask |= 1u << w;
+          }
+        }
+      }
+      const bool on = mask != 0;
+      const uint64_t bal = __ballot(on);
+      const int before = __popcll(bal & ((1ull << lane) - 1ull));
+      if (lane == 0) wcount[wave] = __popcll(bal);
+      __syncthreads();
+      int off = nact;
+      for (int w = 0; w < wave; ++w) off += wcount[w];
+      if (on) {
+        const int e = off + before;
+        const double R = sqrt(ex * ex + ey * ey + ez * ez);
+        const double fr = R * g.fsc;
+        const double fl = floor(fr);
+        eX[e] = (float)ex;
+        eY[e] = (float)ey;
+        eZ[e] = (float)ez;
+        eH[e] = (float)(fr - fl);
+        eK[e] = (int)fl;
+        eM[e] = (int)(m | (mask << 16));
+      }
+      nact += wcount[0] + wcount[1] + wcount[2] + wcount[3];
+      mscan += NT;
+      __syncthreads();
+    }
+
+    for (int q0 = 0; q0 < g.Q; q0 += QN) {
+      const int qn = min(QN, g.Q - q0);
+      __syncthreads();
+      if (t < qn) {
+        const TxRef r = make_tx_ref(g, q0 + t, px, py, pz);
+        qinfo[t] = QInfo{r.vx, r.vy, r.vz, r.vn, r.g, r.ktx, r.kind, 0};
+        ktx_s[t] = r.ktx;
+      }
+      __syncthreads();
+      float bq[QN];
+      float wq[WTX ? QN : 1];
+#pragma unroll
+      for (int q = 0; q < QN; ++q) {
+        bq[q] = 0.f;
+        if (WTX) wq[WTX ? q : 0] = 0.f;
+        if (q < qn) {
+          const QInfo qi = qinfo[q];
+          TxRef r;
+          r.vx = qi.vx; r.vy = qi.vy; r.vz = qi.vz; r.vn = qi.vn; r.kind = qi.kind;
+          bq[q] = fmaf(delta_tx(r, dx, dy, dz, dp2), fscf, qi.g);
+          if (WTX) wq[WTX ? q : 0] = inside ? g.w_tx[(size_t)(q0 + q) * N + n] : 0.f;
+        }
+      }
+
+      Stage<BT, QN, MC> st;
+      if (nact > 0)
+        stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, 0, q0, qn, min(MC, nact), M, K, B, b0, W,
+                                  win.dint, wave, lane);
+      for (int c0 = 0; c0 < nact; c0 += MC) {
+        const int mcn = min(MC, nact - c0);
+        __syncthreads();  // the previous chunk is no longer read
+        stage_store<BT, QN, MC>(st, wsm, mcn, W, wave, lane);
+        __syncthreads();
+        if (c0 + MC < nact)
+          stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, c0 + MC, q0, qn, min(MC, nact - c0 - MC),
+                                    M, K, B, b0, W, win.dint, wave, lane);
+        // ---- interpolate and accumulate ----
+        for (int mc = 0; mc < mcn; ++mc) {
+          const int e = c0 + mc;
+          const int mm = eM[e];
+          if (!(mm & mybit)) continue;  // wavefront-uniform
+          const float ex = eX[e], ey = eY[e], ez = eZ[e];
+          const float ax = ex + dx, ay = ey + dy, az = ez + dz;
+          const float w = rx_weight(g, mm & 0xffff, ax, ay, az);
+          const float en = __builtin_amdgcn_sqrtf(ex * ex + ey * ey + ez * ez);
+          const float a = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, eH[e]);
+          const float* base = wsm + (mc * W + win.dint) * BT;
+          constexpr int QR = QN * BT <= 8 ? QN : (8 / BT < 1 ? 1 : 8 / BT);
+#pragma unroll
+          for (int qa = 0; qa < QN; qa += QR) {
+            float s1[QR][BT], s2[QR][BT], al[QR];
+#pragma unroll
+            for (int r = 0; r < QR; ++r) {
+              const float f = a + bq[qa + r];
+              const float fl = floorf(f);
+              al[r] = f - fl;
+              const float* pp = base + ((qa + r) * MC * W + (int)fl) * BT;
+#pragma unroll
+              for (int b = 0; b < BT; ++b) {
+                s1[r][b] = pp[b];
+                s2[r][b] = pp[BT + b];
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < QR; ++r) {
+              const float wt = WTX ? w * wq[WTX ? qa + r : 0] : w;
+#pragma unroll
+              for (int b = 0; b < BT; ++b)
+                acc[b] = fmaf(wt, fmaf(al[r], s2[r][b], fmaf(-al[r], s1[r][b], s1[r][b])), acc[b]);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (inside) {
+#pragma unroll
+    for (int b = 0; b < BT; ++b)
+      if (b0 + b < B) x[(size_t)(b0 + b) * N + n] = acc[b];
+  }
+}
+
+template <int BT, int QN>
+size_t lds_bytes_t(const Window& w) {
+  return (size_t)layout(QN, chunk_elems<BT, QN>(), BT, w.pairs + 1).total;
+}
+
+template <class T, int BT, int QN, bool WTX>
+hipError_t launch_t(const Geom& g, const TileShape& ts, const Window& w, const void* ws, int B,
+                    float* x, hipStream_t st) {
+  const int ntx = (g.n[0] + ts.tx - 1) / ts.tx, nty = (g.n[1] + ts.ty - 1) / ts.ty,
+            ntz = (g.n[2] + ts.tz - 1) / ts.tz;
+  const int ntiles = ntx * nty * ntz;
+  const int per_xcd = (ntiles + 7) / 8;
+  const size_t lds = lds_bytes_t<BT, QN>(w);
+  dim3 grid(per_xcd * 8, (B + BT - 1) / BT);
+  auto kern = tiled_forward<T, BT, QN, WTX>;
+  if (lds > 65536) {
+    hipError_t e =
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, g, ts, w, static_cast<const T*>(ws), B, x, ntx,
+                     nty, ntiles, per_xcd);
+  return hipGetLastError();
+}
+
+// Transmit-group size for Q transmits.
+inline int group_size(int Q) { return Q == 1 ? 1 : Q <= 4 ? 4 : Q <= 8 ? 8 : 16; }
+
+template <class T, int BT>
+hipError_t launch_bt(const Geom& g, const TileShape& ts, const Window& w, const void* ws, int B,
+                     float* x, hipStream_t st) {
+  const bool wtx = g.w_tx != nullptr;
+  switch (group_size(g.Q)) {
+    case 1: return wtx ? launch_t<T, BT, 1, true>(g, ts, w, ws, B, x, st)
+                       : launch_t<T, BT, 1, false>(g, ts, w, ws, B, x, st);
+    case 4: return wtx ? launch_t<T, BT, 4, true>(g, ts, w, ws, B, x, st)
+                       : launch_t<T, BT, 4, false>(g, ts, w, ws, B, x, st);
+    case 8: return wtx ? launch_t<T, BT, 8, true>(g, ts, w, ws, B, x, st)
+                       : launch_t<T, BT, 8, false>(g, ts, w, ws, B, x, st);
+    default: return wtx ? launch_t<T, BT, 16, true>(g, ts, w, ws, B, x, st)
+                        : launch_t<T, BT, 16, false>(g, ts, w, ws, B, x, st);
+  }
+}
+
+inline size_t lds_bytes(int Q, int bt, const Window& w) {
+  auto pick = [&](auto bt_tag) -> size_t {
+    constexpr int BT = decltype(bt_tag)::value;
+    switch (group_size(Q)) {
+      case 1: return lds_bytes_t<BT, 1>(w);
+      case 4: return lds_bytes_t<BT, 4>(w);
+      case 8: return lds_bytes_t<BT, 8>(w);
+      default: return lds_bytes_t<BT, 16>(w);
+    }
+  };
+  if (bt == 4) return pick(std::integral_constant<int, 4>());
+  if (bt == 2) return pick(std::integral_constant<int, 2>());
+  return pick(std::integral_constant<int, 1>());
+}
+
+template <class T>
+hipError_t launch(const Geom& g, const TileShape& ts, const Window& w, const void* ws, int B,
+                  float* x, hipStream_t st) {
+  const int bt = tiled_batch_per_thread(sizeof(T) == 4 ? DAS_STORE_F32 : DAS_STORE_F16, B);
+  if (bt == 4) return launch_bt<T, 4>(g, ts, w, ws, B, x, st);
+  if (bt == 2) return launch_bt<T, 2>(g, ts, w, ws, B, x, st);
+  return launch_bt<T, 1>(g, ts, w, ws, B, x, st);
+}
+
+}  // namespace tiled
+}  // namespace dasmi

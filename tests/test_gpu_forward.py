@@ -156,16 +156,26 @@ def test_transmit_weights(gpu):
             check_close(x[b], xo[b], REL_L2_F32, ABS_F32, f"w_tx {algo} b={b}")
 
 
-def test_autotune_keeps_result(gpu):
+def test_autotune_and_every_tile_shape(gpu):
+    """Every candidate tile shape meets the FP32 bar; autotuning picks one."""
     das = _das()
-    g = synth.cfg2(dims=(24, 24, 16))
-    y = synth.random_channel_data(g, 1, seed=8).to(gpu)
+    g = synth.cfg2(dims=(19, 17, 9))
+    y = synth.random_channel_data(g, 1, seed=8)
+    xo = oracle.forward(y.numpy(), g)[0]
+    y = y.to(gpu)
     plan = das.Plan(g, max_batch=1, storage="f32", algo="tiled")
-    x0 = plan.forward(y).cpu().numpy()[0]
     t = plan.autotune(1)
     say(f"  autotuned tile {das.das_tile_shape(t)}")
-    x1 = plan.forward(y).cpu().numpy()[0]
-    assert rel_l2(x1, x0) < 2e-6
+    ran = []
     for ti in range(das.das_num_tile_shapes()):
         plan.set_tile(ti)
-        assert rel_l2(plan.forward(y).cpu().numpy()[0], x0) < 2e-6, das.das_tile_shape(ti)
+        try:
+            x = plan.forward(y).cpu().numpy()[0]
+        except das.DasError as e:
+            # shapes whose sample windows exceed one lane per sample are refused
+            assert e.status == das.DAS_ERR_UNSUPPORTED
+            say(f"  tile {das.das_tile_shape(ti)}: unsupported for this geometry")
+            continue
+        check_close(x, xo, REL_L2_F32, ABS_F32, f"tile {das.das_tile_shape(ti)}")
+        ran.append(ti)
+    assert 0 in ran and t in ran
