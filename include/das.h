@@ -111,7 +111,9 @@ das_status das_plan_set_sound_speed(das_plan p, double c);
  * the calls that use it); NULL restores w_tx = 1. */
 das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
 /* Force an algorithm (das_algo) for subsequent calls; AUTO restores the
- * plan's heuristic / tuned choice. */
+ * plan's choice, which is fixed at plan creation (windowed if any tile shape
+ * fits the geometry, else plain).  The algorithm decides the workspace layout:
+ * a workspace must be prepared under the algorithm that reads it. */
 das_status das_plan_set_algo(das_plan p, int32_t algo);
 /* The algorithm das_forward would use for `batch` items. */
 das_status das_plan_get_algo(das_plan p, int32_t batch, int32_t* algo);
@@ -157,7 +159,10 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
  * `stream` (using scratch buffers it allocates and frees) and keep the fastest
  * for this plan.  Synchronizes the stream. */
 das_status das_autotune(das_plan p, int32_t batch, void* stream);
-/* Tile shape index the plan uses for TILED (see das_tile_shape). */
+/* Tile shape index the plan uses for TILED (see das_tile_shape).  set_tile
+ * returns DAS_ERR_UNSUPPORTED, leaving the plan unchanged, for a shape whose
+ * sample windows do not fit this geometry.  The workspace layout does not
+ * depend on the tile shape. */
 das_status das_plan_get_tile(das_plan p, int32_t* tile_index);
 das_status das_plan_set_tile(das_plan p, int32_t tile_index);
 /* Dimensions of candidate tile `tile_index` (0 .. das_num_tile_shapes()-1). */

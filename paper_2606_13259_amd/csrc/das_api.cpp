@@ -125,6 +125,10 @@ struct das_plan_s {
   int algo = DAS_ALGO_AUTO;  // forced algorithm (AUTO = choose)
   int tile = 0;              // index into kTiles
   bool has_diverging = false;
+  // Whether AUTO uses the windowed (batch-inner) workspace layout; fixed at
+  // plan creation so that the layout written by das_prepare and read by
+  // das_forward never depends on later tile or sound-speed changes.
+  bool auto_tiled = false;
 };
 
 namespace {
@@ -186,10 +190,13 @@ hipError_t launch_windowed(const das_plan_s* p, const Geom& g, int tile, const v
   return launch_tiled_forward(g, p->cfg.storage, ts, w, ws, B, x, st);
 }
 
+// The algorithm, and with it the workspace layout, depends only on the forced
+// algorithm and on what was decided at plan creation -- never on the current
+// tile or sound speed -- so das_prepare and das_forward always agree.
 int choose_algo(const das_plan_s* p, int B) {
+  (void)B;
   if (p->algo != DAS_ALGO_AUTO) return p->algo;
-  if (tiled_fits(p, p->tile, B)) return DAS_ALGO_TILED;
-  return DAS_ALGO_PLAIN;
+  return p->auto_tiled ? DAS_ALGO_TILED : DAS_ALGO_PLAIN;
 }
 
 size_t storage_bytes(int storage) { return storage == DAS_STORE_F32 ? 4 : 2; }
@@ -339,6 +346,13 @@ das_status das_plan_create(das_plan* out, const das_config* cfg, int hip_device)
     das_plan_destroy(p);
     return e == hipErrorOutOfMemory ? fail(DAS_ERR_OOM, "hipMalloc failed") : hip_fail(e, "plan upload");
   }
+  for (int ti = 0; ti < kNumTiles; ++ti) {
+    if (tiled_fits(p, ti, 1)) {
+      p->auto_tiled = true;
+      p->tile = ti;
+      break;
+    }
+  }
   *out = p;
   return DAS_OK;
 }
@@ -394,6 +408,8 @@ das_status das_plan_get_tile(das_plan p, int32_t* tile_index) {
 das_status das_plan_set_tile(das_plan p, int32_t tile_index) {
   if (das_status s = check_plan(p)) return s;
   if (tile_index < 0 || tile_index >= kNumTiles) return fail(DAS_ERR_INVALID_ARG, "bad tile index");
+  if (!tiled_fits(p, tile_index, 1))
+    return fail(DAS_ERR_UNSUPPORTED, "the sample windows of this tile shape do not fit (one lane per sample)");
   p->tile = tile_index;
   return DAS_OK;
 }

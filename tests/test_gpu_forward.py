@@ -168,14 +168,43 @@ def test_autotune_and_every_tile_shape(gpu):
     say(f"  autotuned tile {das.das_tile_shape(t)}")
     ran = []
     for ti in range(das.das_num_tile_shapes()):
-        plan.set_tile(ti)
         try:
-            x = plan.forward(y).cpu().numpy()[0]
+            plan.set_tile(ti)
         except das.DasError as e:
             # shapes whose sample windows exceed one lane per sample are refused
             assert e.status == das.DAS_ERR_UNSUPPORTED
             say(f"  tile {das.das_tile_shape(ti)}: unsupported for this geometry")
             continue
-        check_close(x, xo, REL_L2_F32, ABS_F32, f"tile {das.das_tile_shape(ti)}")
+        assert plan.algo(1) == "tiled"
+        check_close(plan.forward(y).cpu().numpy()[0], xo, REL_L2_F32, ABS_F32,
+                    f"tile {das.das_tile_shape(ti)}")
         ran.append(ti)
     assert 0 in ran and t in ran
+
+
+def test_workspace_layout_is_stable(gpu):
+    """Regression: refusing a tile shape must not change the workspace layout
+    that das_forward expects (a half-size f16 workspace was once read as an
+    f32 plain-layout one)."""
+    das = _das()
+    g = synth.cfg2(dims=(16, 16, 8), n_side=16)
+    B = 6
+    y = synth.random_channel_data(g, B, seed=12)
+    xo = oracle.forward(y.numpy(), g)
+    plan = das.Plan(g, max_batch=B, storage="f16")
+    ws = plan.prepare(y.to(gpu))
+    assert ws.numel() == B * g.Q * g.M * g.K * 2
+    refused = 0
+    for ti in range(das.das_num_tile_shapes()):
+        before = plan.tile()
+        try:
+            plan.set_tile(ti)
+        except das.DasError as e:
+            assert e.status == das.DAS_ERR_UNSUPPORTED
+            assert plan.tile() == before
+            refused += 1
+        assert plan.algo(B) == "tiled"
+        x = plan.forward_ws(ws, B).cpu().numpy()
+        for b in (0, B - 1):
+            check_close(x[b], xo[b], REL_L2_LOWP, ABS_LOWP, f"tile {das.das_tile_shape(plan.tile())}")
+    assert refused > 0
