@@ -148,10 +148,14 @@ das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, vo
 das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int32_t batch,
                                 float* dLdc, void* stream);
 
-/* Several forward passes in one persistent launch: for i < count, plan
- * plans[i] beamforms its prepared workspace ws[i] (batch[i] items) into x[i]
- * ([batch[i]][N_i] f32).  All plans must live on the same device and use the
- * TILED layout; their storage types may differ. */
+/* Several forward passes in one persistent launch (the batched form): for
+ * i < count, plan plans[i] beamforms its prepared workspace ws[i] (batch[i]
+ * items) into x[i] ([batch[i]][N_i] f32).  The launch walks one work list of
+ * (plan, voxel tile, batch group) items with a fixed grid of workgroups, each
+ * plan using its own tile shape.  Requirements: 1 <= count <= 16; all plans on
+ * one device with the same storage type, each using the windowed algorithm
+ * (DAS_ERR_UNSUPPORTED otherwise).  Results equal those of das_forward on each
+ * plan. */
 das_status das_forward_batched(int32_t count, const das_plan* plans, const void* const* ws,
                                const int32_t* batch, float* const* x, void* stream);
 

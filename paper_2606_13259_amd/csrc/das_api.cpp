@@ -29,12 +29,9 @@ das_status hip_fail(hipError_t e, const char* what) {
   return fail(DAS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// Candidate voxel tiles of the windowed kernels: indices below kFirstBox are
-// 256-voxel workgroup tiles, the others 64-voxel wavefront boxes.
-const int kTiles[][3] = {{8, 8, 4}, {16, 4, 4}, {4, 8, 8}, {16, 8, 2}, {8, 4, 8}, {16, 16, 1},
-                         {32, 8, 1}, {4, 4, 16}, {4, 4, 4}, {8, 4, 2}, {4, 8, 2}, {8, 8, 1},
-                         {16, 4, 1}, {2, 8, 4}, {4, 2, 8}, {2, 4, 8}};
-constexpr int kFirstBox = 8;
+// Candidate 256-voxel tiles of the windowed kernel (the autotuner's space).
+const int kTiles[][3] = {{8, 8, 4}, {16, 4, 4}, {4, 8, 8}, {16, 8, 2},
+                         {8, 4, 8}, {16, 16, 1}, {32, 8, 1}, {4, 4, 16}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int ilog2(int v) {
@@ -84,22 +81,10 @@ int tiled_batch_per_thread(int storage, int B) {
   return 1;
 }
 
-size_t wave_lds_bytes(const Geom& g, int bt, const Window& w) {
-  const int qn = g.Q == 1 ? 1 : g.Q <= 4 ? 4 : g.Q <= 8 ? 8 : 16;
-  return (size_t)4 * qn * (w.pairs + 1) * bt * 4;
-}
-
 size_t tiled_lds_bytes(const Geom& g, int storage, int bt, const Window& w) {
   if (storage == DAS_STORE_F32) return tiled_lds_f32(g, bt, w);
   if (storage == DAS_STORE_F16) return tiled_lds_f16(g, bt, w);
   return tiled_lds_bf16(g, bt, w);
-}
-
-hipError_t launch_wave_forward(const Geom& g, int storage, const TileShape& ts, const Window& w,
-                               const void* ws, int B, float* x, hipStream_t st) {
-  if (storage == DAS_STORE_F32) return wave_forward_f32(g, ts, w, ws, B, x, st);
-  if (storage == DAS_STORE_F16) return wave_forward_f16(g, ts, w, ws, B, x, st);
-  return wave_forward_bf16(g, ts, w, ws, B, x, st);
 }
 
 hipError_t launch_tiled_forward(const Geom& g, int storage, const TileShape& ts, const Window& w,
@@ -177,7 +162,7 @@ bool tiled_fits(const das_plan_s* p, int tile, int B) {
   const Window w = make_window(p, tile_shape(tile));
   const int st = p->cfg.storage;
   const int bt = tiled_batch_per_thread(st, B);
-  const size_t lds = tile >= kFirstBox ? wave_lds_bytes(g, bt, w) : tiled_lds_bytes(g, st, bt, w);
+  const size_t lds = tiled_lds_bytes(g, st, bt, w);
   // one lane per window sample
   return lds > 0 && lds <= kMaxLds && w.pairs + 1 <= 64;
 }
@@ -186,7 +171,6 @@ hipError_t launch_windowed(const das_plan_s* p, const Geom& g, int tile, const v
                            float* x, hipStream_t st) {
   const TileShape ts = tile_shape(tile);
   const Window w = make_window(p, ts);
-  if (tile >= kFirstBox) return launch_wave_forward(g, p->cfg.storage, ts, w, ws, B, x, st);
   return launch_tiled_forward(g, p->cfg.storage, ts, w, ws, B, x, st);
 }
 
@@ -496,11 +480,56 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
                                const int32_t* batch, float* const* x, void* stream) {
   if (count < 1 || !plans || !ws || !batch || !x)
     return fail(DAS_ERR_INVALID_ARG, "bad batched arguments");
+  if (count > MAX_BATCHED)
+    return fail(DAS_ERR_INVALID_ARG, "at most " + std::to_string(MAX_BATCHED) + " plans per launch");
   for (int i = 0; i < count; ++i) {
     if (!plans[i] || !ws[i] || !x[i]) return fail(DAS_ERR_INVALID_ARG, "NULL entry in batched arguments");
     if (das_status s = check_batch(plans[i], batch[i])) return s;
+    if (plans[i]->device != plans[0]->device)
+      return fail(DAS_ERR_INVALID_ARG, "all plans of a batched launch must be on one device");
+    if (plans[i]->cfg.storage != plans[0]->cfg.storage)
+      return fail(DAS_ERR_UNSUPPORTED, "all plans of a batched launch must share the storage type");
+    if (choose_algo(plans[i], batch[i]) != DAS_ALGO_TILED || !tiled_fits(plans[i], plans[i]->tile, batch[i]))
+      return fail(DAS_ERR_UNSUPPORTED, "batched launches need the windowed algorithm for every plan");
   }
-  return fail(DAS_ERR_UNSUPPORTED, "persistent batched launch not available in this build");
+  DeviceGuard dg(plans[0]->device);
+  const int storage = plans[0]->cfg.storage;
+  int bt = 4, qn = 1;
+  bool wtx = false;
+  for (int i = 0; i < count; ++i) {
+    bt = std::min(bt, tiled_batch_per_thread(storage, batch[i]));
+    const int Q = plans[i]->Q;
+    qn = std::max(qn, Q == 1 ? 1 : Q <= 4 ? 4 : Q <= 8 ? 8 : 16);
+    wtx |= plans[i]->w_tx != nullptr;
+  }
+  BatchedArgs a{};
+  a.count = count;
+  a.first[0] = 0;
+  for (int i = 0; i < count; ++i) {
+    const das_plan_s* p = plans[i];
+    PlanWork& w = a.p[i];
+    w.g = make_geom(p);
+    w.ts = tile_shape(p->tile);
+    w.win = make_window(p, w.ts);
+    w.ws = ws[i];
+    w.x = x[i];
+    w.B = batch[i];
+    w.ntx = (w.g.n[0] + w.ts.tx - 1) / w.ts.tx;
+    w.nty = (w.g.n[1] + w.ts.ty - 1) / w.ts.ty;
+    const int ntz = (w.g.n[2] + w.ts.tz - 1) / w.ts.tz;
+    w.ntiles = w.ntx * w.nty * ntz;
+    a.first[i + 1] = a.first[i] + w.ntiles * ((batch[i] + bt - 1) / bt);
+  }
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plans[0]->device);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  const int grid = std::max(1, std::min(a.first[count], 3 * cus));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (storage == DAS_STORE_F32) e = tiled_batched_f32(a, bt, qn, wtx, grid, st);
+  else if (storage == DAS_STORE_F16) e = tiled_batched_f16(a, bt, qn, wtx, grid, st);
+  else e = tiled_batched_bf16(a, bt, qn, wtx, grid, st);
+  if (e != hipSuccess) return hip_fail(e, "das_forward_batched launch");
+  return DAS_OK;
 }
 
 das_status das_autotune(das_plan p, int32_t batch, void* stream) {

@@ -196,6 +196,15 @@ __device__ inline int cull_elements(const Geom& g, double px, double py, double 
   return nact;
 }
 
+// floor(x) as an integer in one VALU instruction (v_cvt_flr_i32_f32), and the
+// matching fraction x - floor(x) (v_fract_f32).
+__device__ inline int floor_i32(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+__device__ inline float frac_f32(float x) { return __builtin_amdgcn_fractf(x); }
+
 // Voxel-grid helpers.
 __device__ inline int grid_index(const Geom& g, int ix, int iy, int iz) {
   return ix + g.n[0] * (iy + g.n[1] * iz);

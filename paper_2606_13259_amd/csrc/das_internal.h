@@ -41,6 +41,28 @@ struct Window {
   int pairs;             // sample pairs per (transmit, element) window
 };
 
+// One plan's share of a persistent batched launch (passed by value).
+constexpr int MAX_BATCHED = 16;
+struct PlanWork {
+  Geom g;
+  TileShape ts;
+  Window win;
+  const void* ws;
+  float* x;
+  int B, ntx, nty, ntiles;
+};
+struct BatchedArgs {
+  PlanWork p[MAX_BATCHED];
+  int first[MAX_BATCHED + 1];  // work-item ranges per plan
+  int count;
+};
+hipError_t tiled_batched_f32(const BatchedArgs& a, int bt, int qn, bool wtx, int grid,
+                             hipStream_t st);
+hipError_t tiled_batched_f16(const BatchedArgs& a, int bt, int qn, bool wtx, int grid,
+                             hipStream_t st);
+hipError_t tiled_batched_bf16(const BatchedArgs& a, int bt, int qn, bool wtx, int grid,
+                              hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // Host-side launchers (each returns the hipError_t of its launch).
 // ---------------------------------------------------------------------------
@@ -65,19 +87,9 @@ hipError_t tiled_forward_f16(const Geom& g, const TileShape& ts, const Window& w
                              int B, float* x, hipStream_t st);
 hipError_t tiled_forward_bf16(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
                               int B, float* x, hipStream_t st);
-hipError_t wave_forward_f32(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
-                           int B, float* x, hipStream_t st);
-hipError_t wave_forward_f16(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
-                           int B, float* x, hipStream_t st);
-hipError_t wave_forward_bf16(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
-                            int B, float* x, hipStream_t st);
 size_t tiled_lds_f32(const Geom& g, int bt, const Window& w);
 size_t tiled_lds_f16(const Geom& g, int bt, const Window& w);
 size_t tiled_lds_bf16(const Geom& g, int bt, const Window& w);
-
-hipError_t launch_wave_forward(const Geom& g, int storage, const TileShape& ts, const Window& w,
-                               const void* ws, int B, float* x, hipStream_t st);
-size_t wave_lds_bytes(const Geom& g, int bt, const Window& w);
 
 // LDS bytes the tiled forward kernel needs (0 if it cannot run this shape).
 size_t tiled_lds_bytes(const Geom& g, int storage, int bt, const Window& w);

@@ -27,8 +27,11 @@
 //     and weight of a (voxel, element) pair are formed once and reused across
 //     the QN transmits of a group, whose QN LDS reads are all issued before
 //     the first is consumed.
-//   * Block ids are remapped so that each XCD (and its L2) receives a
-//     contiguous range of tiles, whose windows overlap.
+//   * Tiles are dispatched deepest layer first: the cost of a tile grows with
+//     the number of elements whose aperture reaches it (with depth, for an
+//     f-number aperture), so the longest tiles start first and the short
+//     ones fill the tail; consecutive block ids land on different XCDs, so
+//     every XCD receives the same mix of depths.
 //
 // Arithmetic: delays are tile-relative FP32 with FP64 reference terms;
 // samples are converted to FP32 before interpolation; accumulation is FP32.
@@ -42,6 +45,12 @@ namespace tiled {
 
 constexpr int NT = 256;
 constexpr int EMAX = 512;  // active elements held per pass
+constexpr int WS = 64;     // samples per window slot; windows hold W <= WS
+// LDS windows of a chunk are stored [mc][sample][q] with the transmit index
+// innermost and the row padded to QN + 1 entries: the two taps of transmit q
+// are then one ds_read2 with offsets q and q + QN + 1 from a per-lane address,
+// and staging writes of consecutive samples do not collide in one bank.
+template <int QN> struct Row { static constexpr int QP = QN + 1; };
 
 template <class T> __device__ inline float to_f32(T v);
 template <> __device__ inline float to_f32<float>(float v) { return v; }
@@ -69,7 +78,8 @@ struct Layout {
 __host__ __device__ inline Layout layout(int QN, int MC, int BT, int W) {
   Layout L;
   L.win = 0;
-  int o = ((QN * MC * W * BT * 4) + 15) & ~15;
+  (void)W;
+  int o = ((MC * WS * (QN + 1) * BT * 4) + 15) & ~15;
   L.ex = o; o += EMAX * 4;
   L.ey = o; o += EMAX * 4;
   L.ez = o; o += EMAX * 4;
@@ -119,14 +129,18 @@ __device__ inline void stage_load(Stage<BT, QN, MC>& st, const T* __restrict__ w
     const int q = wi / MC, mc = wi % MC;
 #pragma unroll
     for (int b = 0; b < BT; ++b) st.v[k][b] = 0.f;
-    if (wi < QN * MC && q < qn && mc < mcn && lane < W) {
+    if (wi < QN * MC && q < qn && mc < mcn) {
+      // window (q, mc) is wavefront-uniform: scalar base, 32-bit lane offset
       const int e = c0 + mc;
-      const int j = ktx[q] + ek[e] - dint + lane;
-      if (j >= 0 && j < K) {
-        const T* src = ws + (((size_t)(q0 + q) * M + (em[e] & 0xffff)) * (size_t)K + j) * B + b0;
+      const int krx = __builtin_amdgcn_readfirstlane(ek[e]);
+      const int m = __builtin_amdgcn_readfirstlane(em[e]) & 0xffff;
+      const int j0 = __builtin_amdgcn_readfirstlane(ktx[q]) + krx - dint;
+      const T* chan = ws + ((size_t)(q0 + q) * M + m) * (size_t)K * B + b0;
+      const int j = j0 + lane;
+      if (lane < W && j >= 0 && j < K) {
 #pragma unroll
         for (int b = 0; b < BT; ++b)
-          if (b0 + b < B) st.v[k][b] = to_f32<T>(src[b]);
+          if (b0 + b < B) st.v[k][b] = to_f32<T>(chan[j * B + b]);
       }
     }
   }
@@ -136,24 +150,27 @@ template <int BT, int QN, int MC>
 __device__ inline void stage_store(const Stage<BT, QN, MC>& st, float* win, int mcn, int W,
                                    int wave, int lane) {
   constexpr int WPW = Stage<BT, QN, MC>::WPW;
+  constexpr int QP = Row<QN>::QP;
 #pragma unroll
   for (int k = 0; k < WPW; ++k) {
     const int wi = wave + 4 * k;
-    const int mc = wi % MC;
+    const int q = wi / MC, mc = wi % MC;
     if (wi < QN * MC && mc < mcn && lane < W) {
-      float* dst = win + (wi * W + lane) * BT;
+      float* dst = win + ((mc * WS + lane) * QP + q) * BT;
 #pragma unroll
       for (int b = 0; b < BT; ++b) dst[b] = st.v[k][b];
     }
   }
 }
 
+// One tile (tile index `tile`, batch items b0 .. b0+BT-1) of the windowed
+// forward; all 256 threads of the workgroup call it together.
 template <class T, int BT, int QN, bool WTX>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void tiled_forward(
-    Geom g, TileShape ts, Window win, const T* __restrict__ ws, int B, float* __restrict__ x,
-    int ntx, int nty, int ntiles, int per_xcd) {
+__device__ inline void tile_body(const Geom& g, const TileShape& ts, const Window& win,
+                                 const T* __restrict__ ws, int B, float* __restrict__ x, int ntx,
+                                 int nty, int ntiles, int tile, int b0, unsigned char* smem,
+                                 int* ktx_s) {
   constexpr int MC = chunk_elems<BT, QN>();
-  extern __shared__ __align__(16) unsigned char smem[];
   const int W = win.pairs + 1;  // samples per window
   const Layout L = layout(QN, MC, BT, W);
   float* wsm = reinterpret_cast<float*>(smem + L.win);
@@ -165,16 +182,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void ti
   int* eM = reinterpret_cast<int*>(smem + L.em);
   QInfo* qinfo = reinterpret_cast<QInfo*>(smem + L.q);
   int* wcount = reinterpret_cast<int*>(smem + L.wc);
-  __shared__ int ktx_s[16];
 
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
-  const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (tile >= ntiles) return;
-  const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = tile / (ntx * nty);
+  const int ntz = ntiles / (ntx * nty);
+  const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = ntz - 1 - tile / (ntx * nty);
   const int lx = t & (ts.tx - 1), ly = (t >> ts.lx) & (ts.ty - 1), lz = t >> ts.lxy;
   const int ix = tix * ts.tx + lx, iy = tiy * ts.ty + ly, iz = tiz * ts.tz + lz;
-  const int b0 = blockIdx.y * BT;
   const int K = g.K, M = g.M;
   const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
 
@@ -291,7 +305,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void ti
           TxRef r;
           r.vx = qi.vx; r.vy = qi.vy; r.vz = qi.vz; r.vn = qi.vn; r.kind = qi.kind;
           bq[q] = fmaf(delta_tx(r, dx, dy, dz, dp2), fscf, qi.g);
-          if (WTX) wq[WTX ? q : 0] = inside ? g.w_tx[(size_t)(q0 + q) * N + n] : 0.f;
+          if (WTX) wq[WTX ? q : 0] = !inside ? 0.f : g.w_tx ? g.w_tx[(size_t)(q0 + q) * N + n] : 1.f;
         }
       }
 
@@ -310,14 +324,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void ti
         // ---- interpolate and accumulate ----
         for (int mc = 0; mc < mcn; ++mc) {
           const int e = c0 + mc;
-          const int mm = eM[e];
-          if (!(mm & mybit)) continue;  // wavefront-uniform
-          const float ex = eX[e], ey = eY[e], ez = eZ[e];
+          const int mm = __builtin_amdgcn_readfirstlane(eM[e]);
+          if (!(mm & mybit)) continue;  // scalar branch
+          const float ex = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(eX[e])));
+          const float ey = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(eY[e])));
+          const float ez = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(eZ[e])));
+          const float eh = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(eH[e])));
           const float ax = ex + dx, ay = ey + dy, az = ez + dz;
           const float w = rx_weight(g, mm & 0xffff, ax, ay, az);
           const float en = __builtin_amdgcn_sqrtf(ex * ex + ey * ey + ez * ez);
-          const float a = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, eH[e]);
-          const float* base = wsm + (mc * W + win.dint) * BT;
+          const float a = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, eh);
+          constexpr int QP = Row<QN>::QP;
+          // tap index i = floor(f) + dint is in [1, 2 dint + 1] (window bound)
+          const float* base = wsm + (mc * WS + win.dint) * QP * BT;
           constexpr int QR = QN * BT <= 8 ? QN : (8 / BT < 1 ? 1 : 8 / BT);
 #pragma unroll
           for (int qa = 0; qa < QN; qa += QR) {
@@ -325,15 +344,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void ti
 #pragma unroll
             for (int r = 0; r < QR; ++r) {
               const float f = a + bq[qa + r];
-              const float fl = floorf(f);
-              al[r] = f - fl;
-              const float* pp = base + ((qa + r) * MC * W + (int)fl) * BT;
+              al[r] = frac_f32(f);
+              const float* pp = base + (__mul24(floor_i32(f), QP * BT) + (qa + r) * BT);
 #pragma unroll
               for (int b = 0; b < BT; ++b) {
                 s1[r][b] = pp[b];
-                s2[r][b] = pp[BT + b];
+                s2[r][b] = pp[QP * BT + b];
               }
             }
+            __builtin_amdgcn_sched_barrier(0);  // all reads of the group issue first
 #pragma unroll
             for (int r = 0; r < QR; ++r) {
               const float wt = WTX ? w * wq[WTX ? qa + r : 0] : w;
@@ -353,6 +372,39 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void ti
   }
 }
 
+template <class T, int BT, int QN, bool WTX>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void tiled_forward(
+    Geom g, TileShape ts, Window win, const T* __restrict__ ws, int B, float* __restrict__ x,
+    int ntx, int nty, int ntiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int ktx_s[16];
+  tile_body<T, BT, QN, WTX>(g, ts, win, ws, B, x, ntx, nty, ntiles, blockIdx.x, blockIdx.y * BT,
+                            smem, ktx_s);
+}
+
+// Several forward passes in one persistent launch: workgroup w processes work
+// items w, w + gridDim.x, ...; item i belongs to the plan p whose range
+// [first[p], first[p+1]) contains it and names one (tile, batch group) of that
+// plan (tiles deepest first, batch groups outermost).
+
+template <class T, int BT, int QN, bool WTX>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void tiled_forward_batched(
+    BatchedArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int ktx_s[16];
+  const int total = a.first[a.count];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int p = 0;
+    while (p + 1 < a.count && item >= a.first[p + 1]) ++p;
+    const PlanWork& w = a.p[p];
+    const int local = item - a.first[p];
+    const int tile = local % w.ntiles, bg = local / w.ntiles;
+    __syncthreads();  // the previous item no longer reads LDS
+    tile_body<T, BT, QN, WTX>(w.g, w.ts, w.win, static_cast<const T*>(w.ws), w.B, w.x, w.ntx,
+                              w.nty, w.ntiles, tile, bg * BT, smem, ktx_s);
+  }
+}
+
 template <int BT, int QN>
 size_t lds_bytes_t(const Window& w) {
   return (size_t)layout(QN, chunk_elems<BT, QN>(), BT, w.pairs + 1).total;
@@ -364,9 +416,8 @@ hipError_t launch_t(const Geom& g, const TileShape& ts, const Window& w, const v
   const int ntx = (g.n[0] + ts.tx - 1) / ts.tx, nty = (g.n[1] + ts.ty - 1) / ts.ty,
             ntz = (g.n[2] + ts.tz - 1) / ts.tz;
   const int ntiles = ntx * nty * ntz;
-  const int per_xcd = (ntiles + 7) / 8;
   const size_t lds = lds_bytes_t<BT, QN>(w);
-  dim3 grid(per_xcd * 8, (B + BT - 1) / BT);
+  dim3 grid(ntiles, (B + BT - 1) / BT);
   auto kern = tiled_forward<T, BT, QN, WTX>;
   if (lds > 65536) {
     hipError_t e =
@@ -374,7 +425,7 @@ hipError_t launch_t(const Geom& g, const TileShape& ts, const Window& w, const v
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, g, ts, w, static_cast<const T*>(ws), B, x, ntx,
-                     nty, ntiles, per_xcd);
+                     nty, ntiles);
   return hipGetLastError();
 }
 
@@ -419,6 +470,42 @@ hipError_t launch(const Geom& g, const TileShape& ts, const Window& w, const voi
   if (bt == 4) return launch_bt<T, 4>(g, ts, w, ws, B, x, st);
   if (bt == 2) return launch_bt<T, 2>(g, ts, w, ws, B, x, st);
   return launch_bt<T, 1>(g, ts, w, ws, B, x, st);
+}
+
+template <class T, int BT, int QN, bool WTX>
+hipError_t launch_batched_t(const BatchedArgs& a, int grid, hipStream_t st) {
+  const Window w0{0, 63};
+  const size_t lds = lds_bytes_t<BT, QN>(w0);
+  auto kern = tiled_forward_batched<T, BT, QN, WTX>;
+  if (lds > 65536) {
+    hipError_t e =
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, a);
+  return hipGetLastError();
+}
+
+template <class T, int BT>
+hipError_t launch_batched_bt(const BatchedArgs& a, int qn, bool wtx, int grid, hipStream_t st) {
+  switch (qn) {
+    case 1: return wtx ? launch_batched_t<T, BT, 1, true>(a, grid, st)
+                       : launch_batched_t<T, BT, 1, false>(a, grid, st);
+    case 4: return wtx ? launch_batched_t<T, BT, 4, true>(a, grid, st)
+                       : launch_batched_t<T, BT, 4, false>(a, grid, st);
+    case 8: return wtx ? launch_batched_t<T, BT, 8, true>(a, grid, st)
+                       : launch_batched_t<T, BT, 8, false>(a, grid, st);
+    default: return wtx ? launch_batched_t<T, BT, 16, true>(a, grid, st)
+                        : launch_batched_t<T, BT, 16, false>(a, grid, st);
+  }
+}
+
+template <class T>
+hipError_t launch_batched(const BatchedArgs& a, int bt, int qn, bool wtx, int grid,
+                          hipStream_t st) {
+  if (bt == 4) return launch_batched_bt<T, 4>(a, qn, wtx, grid, st);
+  if (bt == 2) return launch_batched_bt<T, 2>(a, qn, wtx, grid, st);
+  return launch_batched_bt<T, 1>(a, qn, wtx, grid, st);
 }
 
 }  // namespace tiled

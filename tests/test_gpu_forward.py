@@ -208,3 +208,29 @@ def test_workspace_layout_is_stable(gpu):
         for b in (0, B - 1):
             check_close(x[b], xo[b], REL_L2_LOWP, ABS_LOWP, f"tile {das.das_tile_shape(plan.tile())}")
     assert refused > 0
+
+
+def test_persistent_batched_launch(gpu):
+    """One persistent launch over plans with different grids, arrays,
+    transmit counts and batch sizes equals separate launches and the oracle."""
+    das = _das()
+    geoms = [synth.cfg2(dims=(13, 10, 7), n_side=8).replace(num_samples=1600),
+             synth.sub_grid(synth.cfg5(), (20, 24, 10), (9, 8, 12)),
+             synth.cfg1()]
+    batches = [2, 3, 1]
+    plans, wss, xs, ys = [], [], [], []
+    for g, B in zip(geoms, batches):
+        y = synth.random_channel_data(g, B, seed=20 + B)
+        p = das.Plan(g, max_batch=B, storage="f32")
+        ws = p.prepare(y.to(gpu))
+        plans.append(p)
+        wss.append(ws)
+        xs.append(torch.full((B, p.N), float("nan"), device=gpu))
+        ys.append(y)
+    das.das_forward_batched([p.handle for p in plans], wss, batches, xs)
+    for p, ws, x, y, g, B in zip(plans, wss, xs, ys, geoms, batches):
+        xsep = p.forward_ws(ws, B)
+        assert torch.equal(x, xsep), "batched launch differs from a separate launch"
+        xo = oracle.forward(y.numpy(), g)
+        for b in range(B):
+            check_close(x[b].cpu().numpy(), xo[b], REL_L2_F32, ABS_F32, f"batched {g.grid_dims} b={b}")
