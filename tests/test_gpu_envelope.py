@@ -1,0 +1,78 @@
+"""Envelope, image-quality metrics and sound-speed autofocus on the MI355X,
+against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import envelope as oenv
+from paper_2606_13259_amd import metrics
+from tests.gpu_util import cfg2_channel_data, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _das():
+    from paper_2606_13259_amd import das
+    return das
+
+
+def _block_around(g, pos, half=8):
+    c = np.rint((np.asarray(pos) - np.asarray(g.grid_origin)) / np.asarray(g.grid_spacing)).astype(int)
+    start = np.clip(c - half, 0, np.asarray(g.grid_dims) - 2 * half)
+    return synth.sub_grid(g, start, (2 * half, 2 * half, 2 * half))
+
+
+@pytest.mark.parametrize("storage,max_db,mean_db", [("f32", 0.01, 0.001), ("f16", 1.0, 0.05),
+                                                    ("bf16", 3.0, 0.3)])
+def test_envelope_and_point_targets_cfg2(gpu, storage, max_db, mean_db):
+    """Envelope-dB error (voxels within 40 dB of the peak) and point-target
+    peak / -6 dB widths of the precision forms vs the oracle, on a 16^3 block
+    around one of the cfg2 point targets."""
+    das = _das()
+    g, y = cfg2_channel_data()
+    targets = synth.scatterers(g, 200, 0, seed_targets=3, seed_speckle=4).pos[:200]
+    # a target near the middle of the volume
+    tgt = targets[np.argmin(np.abs(targets[:, 2] - 11e-3))]
+    sub = _block_around(g, tgt)
+    env_o = oenv.envelope(y.cpu().numpy(), sub).reshape(16, 16, 16)
+    plan = das.Plan(sub, max_batch=2, storage=storage)
+    lanes = metrics.analytic_lanes(y).contiguous()
+    x = plan.forward(lanes)
+    env = metrics.envelope(x[0], x[1]).reshape(16, 16, 16)
+    mx, mean = metrics.envelope_db_error(env, torch.from_numpy(env_o), floor_db=-40)
+    (p, w), = metrics.point_targets(env, sub.grid_origin, sub.grid_spacing, [tgt])
+    (po, wo), = metrics.point_targets(torch.from_numpy(env_o), sub.grid_origin, sub.grid_spacing, [tgt])
+    say(f"  {storage}: envelope dB error max {mx:.4f} mean {mean:.5f}; peak diff "
+        f"{np.abs(p - po).max() * 1e6:.3f} um; width diff {np.abs(w - wo).max() * 1e6:.3f} um")
+    assert mx <= max_db and mean <= mean_db
+    assert np.abs(p - po).max() <= 0.01 * sub.grid_spacing[0]
+    assert np.abs(w - wo).max() <= 0.02 * sub.grid_spacing[0]
+
+
+def test_autofocus_converges_to_scan_argmax(gpu):
+    """cfg5 (data made at 1500 m/s), starting at 1540 m/s: the gradient loop on
+    the GPU converges to the argmax of a brute-force scan of the oracle's
+    envelope energy over [1480, 1560] m/s (0.5 m/s resolution)."""
+    from paper_2606_13259_amd import autofocus
+    das = _das()
+    g, s, y = synth.cfg5_data(device="cuda:0")
+    tgt = s.pos[int(np.argmax(s.amp[:50]))]
+    sub = _block_around(g, tgt, half=5)
+    yc = y.cpu().numpy()
+    lanes_o = oenv.analytic_lanes(yc)
+
+    def L(c):
+        x = oracle.forward(lanes_o, sub, c=c)
+        return float(np.sum(x ** 2))
+
+    coarse = np.arange(1480.0, 1560.0 + 1e-9, 2.0)
+    lc = [L(c) for c in coarse]
+    c1 = coarse[int(np.argmax(lc))]
+    fine = np.arange(c1 - 2.0, c1 + 2.0 + 1e-9, 0.5)
+    c_best = fine[int(np.argmax([L(c) for c in fine]))]
+    plan = das.Plan(sub, max_batch=2, storage="f32")
+    c_gpu, hist = autofocus.autofocus(plan, y, c0=1540.0)
+    say(f"  scan argmax {c_best:.1f} m/s; autofocus {c_gpu:.2f} m/s after {len(hist)} steps")
+    assert abs(c_gpu - c_best) <= 0.5
