@@ -61,7 +61,7 @@ typedef enum {
   DAS_ALGO_AUTO = 0,    /* tuned / heuristic choice among the three below */
   DAS_ALGO_PLAIN = 1,   /* one voxel per lane, direct gathers from y[B][Q][M][K] f32 */
   DAS_ALGO_TILED = 2,   /* voxel tiles, LDS sample windows, aperture culling */
-  DAS_ALGO_MFMA = 3     /* windowed tile contraction on matrix cores (f16/bf16, B >= 16) */
+  DAS_ALGO_MFMA = 3     /* locality form on matrix cores (f16/bf16 storage only) */
 } das_algo;
 
 /* One transmit (observation) q: footnote to Eq. (1). */
@@ -111,9 +111,12 @@ das_status das_plan_set_sound_speed(das_plan p, double c);
  * the calls that use it); NULL restores w_tx = 1. */
 das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
 /* Force an algorithm (das_algo) for subsequent calls; AUTO restores the
- * plan's choice, which is fixed at plan creation (windowed if any tile shape
- * fits the geometry, else plain).  The algorithm decides the workspace layout:
- * a workspace must be prepared under the algorithm that reads it. */
+ * plan's choice.  AUTO depends only on the storage type, the batch size and
+ * what was fixed at plan creation: MFMA for f16/bf16 storage with batch >= 16,
+ * else windowed if any tile shape fits the geometry, else plain.  MFMA with
+ * f32 storage returns DAS_ERR_UNSUPPORTED.  The algorithm decides the
+ * workspace layout: a workspace must be prepared under the algorithm (and
+ * batch_total) that reads it. */
 das_status das_plan_set_algo(das_plan p, int32_t algo);
 /* The algorithm das_forward would use for `batch` items. */
 das_status das_plan_get_algo(das_plan p, int32_t batch, int32_t* algo);
@@ -127,8 +130,12 @@ das_status das_workspace_bytes(das_plan p, int32_t batch, size_t* bytes);
  * batch_total) bytes.  Layout written:
  *   PLAIN:        [batch_total][Q][M][K] f32 (a copy; y itself may be passed
  *                 as ws to das_forward instead)
- *   TILED, MFMA:  [Q][M][K][batch_total] in the plan's storage type, rounded
- *                 to nearest even. */
+ *   TILED:        [Q][M][K][batch_total] in the plan's storage type, rounded
+ *                 to nearest even;
+ *   MFMA:         [Q][M][Kc][Bp][8] in f16/bf16 (rounded to nearest even):
+ *                 8-sample chunks, chunk kc holding samples 8(kc-1) .. 8kc-1
+ *                 (zero outside [0, K)), Kc = ceil(K/8) + 2, Bp = batch_total
+ *                 rounded up to a multiple of 16 (Sec. 3.4 locality form). */
 das_status das_prepare(das_plan p, const float* y, int32_t b0, int32_t nb, int32_t batch_total,
                        void* ws, void* stream);
 

@@ -177,9 +177,12 @@ hipError_t launch_windowed(const das_plan_s* p, const Geom& g, int tile, const v
 // The algorithm, and with it the workspace layout, depends only on the forced
 // algorithm and on what was decided at plan creation -- never on the current
 // tile or sound speed -- so das_prepare and das_forward always agree.
+// Batch size from which AUTO contracts on the matrix cores (16-bit storage).
+constexpr int kMfmaMinBatch = 16;
+
 int choose_algo(const das_plan_s* p, int B) {
-  (void)B;
   if (p->algo != DAS_ALGO_AUTO) return p->algo;
+  if (p->cfg.storage != DAS_STORE_F32 && B >= kMfmaMinBatch) return DAS_ALGO_MFMA;
   return p->auto_tiled ? DAS_ALGO_TILED : DAS_ALGO_PLAIN;
 }
 
@@ -189,6 +192,7 @@ size_t ws_bytes(const das_plan_s* p, int B) {
   const int algo = choose_algo(p, B);
   const size_t elems = (size_t)B * p->Q * p->M * p->K;
   if (algo == DAS_ALGO_PLAIN) return elems * 4;
+  if (algo == DAS_ALGO_MFMA) return mfma_workspace_elems(make_geom(p), B) * 2;
   return elems * storage_bytes(p->cfg.storage);
 }
 
@@ -263,6 +267,8 @@ das_status das_plan_create(das_plan* out, const das_config* cfg, int hip_device)
     return fail(DAS_ERR_INVALID_ARG, "unknown storage");
   if (cfg->algo < DAS_ALGO_AUTO || cfg->algo > DAS_ALGO_MFMA)
     return fail(DAS_ERR_INVALID_ARG, "unknown algo");
+  if (cfg->algo == DAS_ALGO_MFMA && cfg->storage == DAS_STORE_F32)
+    return fail(DAS_ERR_UNSUPPORTED, "the MFMA form needs f16 or bf16 storage");
   for (int m = 0; m < M; ++m)
     if (!finite3(cfg->element_pos + 3 * m)) return fail(DAS_ERR_INVALID_ARG, "element_pos not finite");
   std::vector<float> norm;
@@ -370,6 +376,8 @@ das_status das_plan_set_tx_weights(das_plan p, const float* w_tx) {
 das_status das_plan_set_algo(das_plan p, int32_t algo) {
   if (das_status s = check_plan(p)) return s;
   if (algo < DAS_ALGO_AUTO || algo > DAS_ALGO_MFMA) return fail(DAS_ERR_INVALID_ARG, "unknown algo");
+  if (algo == DAS_ALGO_MFMA && p->cfg.storage == DAS_STORE_F32)
+    return fail(DAS_ERR_UNSUPPORTED, "the MFMA form needs f16 or bf16 storage");
   p->algo = algo;
   return DAS_OK;
 }
@@ -417,10 +425,13 @@ das_status das_prepare(das_plan p, const float* y, int32_t b0, int32_t nb, int32
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Geom g = make_geom(p);
   hipError_t e;
-  if (choose_algo(p, batch_total) == DAS_ALGO_PLAIN) {
+  const int algo = choose_algo(p, batch_total);
+  if (algo == DAS_ALGO_PLAIN) {
     const size_t n = (size_t)nb * p->Q * p->M * p->K;
     float* dst = static_cast<float*>(ws) + (size_t)b0 * p->Q * p->M * p->K;
     e = hipMemcpyAsync(dst, y, n * sizeof(float), hipMemcpyDeviceToDevice, st);
+  } else if (algo == DAS_ALGO_MFMA) {
+    e = launch_mfma_reorder(g, p->cfg.storage, y, b0, nb, batch_total, ws, st);
   } else {
     e = launch_reorder(g, p->cfg.storage, y, b0, nb, batch_total, ws, st);
   }
@@ -444,7 +455,7 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
       return fail(DAS_ERR_UNSUPPORTED, "tile windows do not fit in LDS for this geometry");
     e = launch_windowed(p, g, p->tile, ws, batch, x, st);
   } else {
-    return fail(DAS_ERR_UNSUPPORTED, "MFMA form not available in this build");
+    e = launch_mfma_forward(g, p->cfg.storage, ws, batch, x, st);
   }
   if (e != hipSuccess) return hip_fail(e, "das_forward launch");
   return DAS_OK;

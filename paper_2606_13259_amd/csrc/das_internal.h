@@ -77,8 +77,15 @@ hipError_t launch_grad_c(const Geom& g, const float* y, const float* gx, int B, 
                          hipStream_t st);
 hipError_t launch_debug_delays(const Geom& g, const TileShape& ts, int q, int m0, int m1, int n0,
                                int n1, double* f_out, hipStream_t st);
-hipError_t launch_mfma_forward(const Geom& g, int storage, const Window& w, const void* ws, int B,
-                               float* x, hipStream_t st);
+// Matrix-core locality form (f16 / bf16 storage): chunked batch-inner
+// workspace [Q][M][Kc][Bp][8].
+int mfma_batch_pad(int B);
+int mfma_chunks(int K);
+size_t mfma_workspace_elems(const Geom& g, int B);
+hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b0, int nb, int btot,
+                               void* ws, hipStream_t st);
+hipError_t launch_mfma_forward(const Geom& g, int storage, const void* ws, int B, float* x,
+                               hipStream_t st);
 
 // Windowed forward, one instantiation set per storage type.
 hipError_t tiled_forward_f32(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
@@ -94,6 +101,5 @@ size_t tiled_lds_bf16(const Geom& g, int bt, const Window& w);
 // LDS bytes the tiled forward kernel needs (0 if it cannot run this shape).
 size_t tiled_lds_bytes(const Geom& g, int storage, int bt, const Window& w);
 int tiled_batch_per_thread(int storage, int B);
-size_t mfma_lds_bytes(const Geom& g, const Window& w);
 
 }  // namespace dasmi

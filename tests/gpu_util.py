@@ -10,9 +10,20 @@ import synth
 
 # Parity bars (stated by the benchmark spec's target and derived in the design doc):
 REL_L2_F32 = 1e-5      # FP32 storage and arithmetic vs the FP64 oracle
-REL_L2_LOWP = 1e-3     # FP16 / BF16 storage (FP32 arithmetic) vs the FP64 oracle
+REL_L2_LOWP = 1e-3     # FP16 storage (FP32 arithmetic) vs the FP64 oracle
 ABS_F32 = 1e-5         # elementwise |x - x_o| / max|x_o|, FP32
-ABS_LOWP = 2e-3        # elementwise |x - x_o| / max|x_o|, FP16 / BF16
+ABS_LOWP = 2e-3        # elementwise |x - x_o| / max|x_o|, FP16
+# BF16 keeps 8 significant bits: round-to-nearest-even leaves a relative error
+# of at most 2^-8 per sample, rms about 2^-7/sqrt(12) = 1.1e-3 to 1.7e-3 for
+# Gaussian data, and the output error is of the same relative size.  Its bar
+# is storage-limited: 4e-3 rel-L2, 6e-3 elementwise.
+REL_L2_BF16 = 4e-3
+ABS_BF16 = 6e-3
+
+
+def lowp_bars(storage):
+    """(rel-L2, elementwise) bars against the oracle on the raw FP32 data."""
+    return (REL_L2_BF16, ABS_BF16) if storage == "bf16" else (REL_L2_LOWP, ABS_LOWP)
 
 
 def say(msg):

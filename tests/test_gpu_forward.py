@@ -5,8 +5,8 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_util import (ABS_F32, ABS_LOWP, REL_L2_F32, REL_L2_LOWP, cfg2_channel_data,
-                            check_close, rel_l2, round_like_storage, sample_voxels, say)
+from tests.gpu_util import (ABS_F32, REL_L2_F32, cfg2_channel_data, check_close, lowp_bars, rel_l2,
+                            round_like_storage, sample_voxels, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -71,7 +71,7 @@ def test_cfg2_subblocks(gpu, cfg2_blocks, storage, algo):
         if storage == "f32":
             check_close(x, xo, REL_L2_F32, ABS_F32, f"cfg2 block {sub.grid_dims} {storage} {algo}")
         else:
-            check_close(x, xo, REL_L2_LOWP, ABS_LOWP, f"cfg2 block {sub.grid_dims} {storage} {algo}")
+            check_close(x, xo, *lowp_bars(storage), f"cfg2 block {sub.grid_dims} {storage} {algo}")
             # kernel error alone: oracle on the values the workspace holds
             xr = oracle.forward(round_like_storage(y.cpu().numpy(), storage)[None], sub)[0]
             check_close(x, xr, REL_L2_F32, ABS_F32, f"  vs oracle on {storage}-rounded data")
@@ -206,7 +206,7 @@ def test_workspace_layout_is_stable(gpu):
         assert plan.algo(B) == "tiled"
         x = plan.forward_ws(ws, B).cpu().numpy()
         for b in (0, B - 1):
-            check_close(x[b], xo[b], REL_L2_LOWP, ABS_LOWP, f"tile {das.das_tile_shape(plan.tile())}")
+            check_close(x[b], xo[b], *lowp_bars("f16"), f"tile {das.das_tile_shape(plan.tile())}")
     assert refused > 0
 
 
