@@ -132,10 +132,12 @@ das_status das_workspace_bytes(das_plan p, int32_t batch, size_t* bytes);
  *                 as ws to das_forward instead)
  *   TILED:        [Q][M][K][batch_total] in the plan's storage type, rounded
  *                 to nearest even;
- *   MFMA:         [Q][M][Kc][Bp][8] in f16/bf16 (rounded to nearest even):
- *                 8-sample chunks, chunk kc holding samples 8(kc-1) .. 8kc-1
- *                 (zero outside [0, K)), Kc = ceil(K/8) + 2, Bp = batch_total
- *                 rounded up to a multiple of 16 (Sec. 3.4 locality form). */
+ *   MFMA:         [Bp/TW][Q][M][Kc][TW][8] in f16/bf16 (rounded to nearest
+ *                 even): 8-sample chunks, chunk kc holding samples
+ *                 8(kc-1) .. 8kc-1 (zero outside [0, K)), Kc = ceil(K/8) + 2;
+ *                 batch tiles of TW = 16, 32 or 64 items for batch_total
+ *                 <= 16, <= 32 or more, Bp = batch_total rounded up to TW
+ *                 (Sec. 3.4 locality form). */
 das_status das_prepare(das_plan p, const float* y, int32_t b0, int32_t nb, int32_t batch_total,
                        void* ws, void* stream);
 

@@ -21,9 +21,11 @@ def envelope_energy(plan: "das.Plan", lanes: torch.Tensor, c: torch.Tensor) -> t
 
 
 def autofocus(plan: "das.Plan", y: torch.Tensor, c0: float, steps: int = 80, lr: float = 3.0,
-              decay: float = 0.95, lanes: torch.Tensor | None = None):
+              decay: float = 0.95, lanes: torch.Tensor | None = None,
+              bounds: tuple[float, float] | None = None):
     """Maximise the envelope energy over c, starting from c0 (m/s), with Adam
-    and an exponentially decaying step (lr * decay^t, in m/s).
+    and an exponentially decaying step (lr * decay^t, in m/s); with
+    ``bounds`` = (c_min, c_max) every step is projected onto that interval.
 
     y: real channel data [Q, M, K] (ignored when ``lanes`` is given).
     Returns (c, history) with history a list of (c, L) per step."""
@@ -44,5 +46,8 @@ def autofocus(plan: "das.Plan", y: torch.Tensor, c0: float, steps: int = 80, lr:
         (-L / L0).backward()           # ascend; normalised so lr is in m/s
         hist.append((float(c.detach()), float(L.detach())))
         opt.step()
+        if bounds is not None:
+            with torch.no_grad():
+                c.clamp_(float(bounds[0]), float(bounds[1]))
         sched.step()
     return float(c.detach()), hist

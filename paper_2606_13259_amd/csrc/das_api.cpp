@@ -487,6 +487,28 @@ das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int
   return DAS_OK;
 }
 
+// Persistent MFMA launch over several plans (all validated by the caller).
+static das_status forward_batched_mfma(int32_t count, const das_plan* plans, const void* const* ws,
+                                       const int32_t* batch, float* const* x, void* stream) {
+  MfmaBatchedArgs a{};
+  a.count = count;
+  for (int i = 0; i < count; ++i) {
+    MfmaWork& w = a.p[i];
+    w.g = make_geom(plans[i]);
+    w.ws = ws[i];
+    w.x = x[i];
+    w.B = batch[i];
+    w.TW = mfma_tile_width(batch[i]);
+    w.Kc = mfma_chunks(w.g.K);
+  }
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plans[0]->device);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  e = launch_mfma_batched(a, plans[0]->cfg.storage, cus, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "das_forward_batched launch");
+  return DAS_OK;
+}
+
 das_status das_forward_batched(int32_t count, const das_plan* plans, const void* const* ws,
                                const int32_t* batch, float* const* x, void* stream) {
   if (count < 1 || !plans || !ws || !batch || !x)
@@ -500,11 +522,20 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
       return fail(DAS_ERR_INVALID_ARG, "all plans of a batched launch must be on one device");
     if (plans[i]->cfg.storage != plans[0]->cfg.storage)
       return fail(DAS_ERR_UNSUPPORTED, "all plans of a batched launch must share the storage type");
-    if (choose_algo(plans[i], batch[i]) != DAS_ALGO_TILED || !tiled_fits(plans[i], plans[i]->tile, batch[i]))
-      return fail(DAS_ERR_UNSUPPORTED, "batched launches need the windowed algorithm for every plan");
+  }
+  const int algo0 = choose_algo(plans[0], batch[0]);
+  for (int i = 0; i < count; ++i) {
+    const int algo = choose_algo(plans[i], batch[i]);
+    if (algo != algo0)
+      return fail(DAS_ERR_UNSUPPORTED, "all plans of a batched launch must use the same algorithm");
+    if (algo == DAS_ALGO_PLAIN)
+      return fail(DAS_ERR_UNSUPPORTED, "batched launches need the windowed or MFMA algorithm");
+    if (algo == DAS_ALGO_TILED && !tiled_fits(plans[i], plans[i]->tile, batch[i]))
+      return fail(DAS_ERR_UNSUPPORTED, "tile windows do not fit for a plan of the batched launch");
   }
   DeviceGuard dg(plans[0]->device);
   const int storage = plans[0]->cfg.storage;
+  if (algo0 == DAS_ALGO_MFMA) return forward_batched_mfma(count, plans, ws, batch, x, stream);
   int bt = 4, qn = 1;
   bool wtx = false;
   for (int i = 0; i < count; ++i) {

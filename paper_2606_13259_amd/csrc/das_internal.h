@@ -79,8 +79,25 @@ hipError_t launch_debug_delays(const Geom& g, const TileShape& ts, int q, int m0
                                int n1, double* f_out, hipStream_t st);
 // Matrix-core locality form (f16 / bf16 storage): chunked batch-inner
 // workspace [Q][M][Kc][Bp][8].
-int mfma_batch_pad(int B);
+int mfma_tiles_per_wave(int B);  // 16-column MFMA tiles per wavefront (1, 2 or 4)
+int mfma_tile_width(int B);      // batch items per workspace tile (16 x tiles per wavefront)
+int mfma_batch_pad(int B);       // batch rounded up to the tile width
 int mfma_chunks(int K);
+// One plan's share of a persistent MFMA launch (passed by value).
+struct MfmaWork {
+  Geom g;
+  const void* ws;
+  float* x;
+  int B, TW, Kc, ngx, ngy, ngroups, nbx;
+};
+struct MfmaBatchedArgs {
+  MfmaWork p[MAX_BATCHED];
+  int first[MAX_BATCHED + 1];  // work-item ranges per plan
+  int count;
+};
+// Fills the derived fields (column counts, work-list ranges) of `a` from
+// g, ws, x, B, TW, Kc of each plan and launches the persistent MFMA kernel.
+hipError_t launch_mfma_batched(MfmaBatchedArgs& a, int storage, int cus, hipStream_t st);
 size_t mfma_workspace_elems(const Geom& g, int B);
 hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b0, int nb, int btot,
                                void* ws, hipStream_t st);

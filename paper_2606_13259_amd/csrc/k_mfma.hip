@@ -19,14 +19,21 @@
 // are culled first (conservative sphere-cone test), and quads are formed from
 // the surviving receivers.
 //
-// Workspace ("chunked batch-inner"): ws[q][m][kc][Bp][8] in f16 or bf16, chunk
-// kc holding samples 8 (kc - 1) .. 8 kc - 1 (zero outside [0, K)), Kc =
-// ceil(K/8) + 2 chunks, Bp = batch rounded up to 16.  The B fragment of a
-// lane (batch item b, receiver row r) is one 16-byte load, and the 16 lanes of
-// a row read 256 contiguous bytes.
+// Workspace ("batch-tiled chunks"): ws[Bp/TW][q][m][kc][TW][8] in f16 or bf16,
+// chunk kc holding samples 8 (kc - 1) .. 8 kc - 1 (zero outside [0, K)),
+// Kc = ceil(K/8) + 2 chunks, TW = 16 NB batch items per tile (NB = 1, 2, 4 by
+// batch size) and Bp the batch rounded up to TW.  The B fragment of a lane
+// (batch item b, receiver row r) is one 16-byte load, the 16 lanes of a row
+// read 256 contiguous bytes, and the wavefronts of one batch tile sweep one
+// contiguous region.
+//
+// A wavefront owns a column of kStack such groups stacked in depth: it loads
+// the union of their chunks once per receiver row and applies each loaded
+// chunk to every group of the column with taps in it, which divides the
+// L1/L2 traffic (the bound of this form) by up to the stack depth.
 //
 // Delay formation is the tile-relative FP32 scheme of the VALU kernels with
-// the group centre as reference.  Weights are rounded to the operand type;
+// the group (or column) centre as reference.  Weights are rounded to the operand type;
 // for bf16 each weight is split into a high and a low bf16 part (two MFMAs
 // with the same samples) so that the weight rounding stays far below the
 // storage rounding.  Accumulation is FP32.
@@ -86,22 +93,6 @@ __device__ inline u32x4 place_pair(uint32_t P, int d) {
   return u32x4{(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
 }
 
-// Min / max over the 16 lanes of a DPP row (rotations by 1, 2, 4, 8).
-__device__ inline int row_min(int v) {
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x121, 0xf, 0xf, false));
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x122, 0xf, 0xf, false));
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xf, 0xf, false));
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false));
-  return v;
-}
-__device__ inline int row_max(int v) {
-  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x121, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x122, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false));
-  return v;
-}
-
 // Can any point of the sphere (centre p0, radius R) lie in the receive cone of
 // the element (e = p0 - r_m, axis n, half-angle with cos cth, sin sth)?
 // Conservative and trig-free: cos(phi) > cos(theta + beta).
@@ -116,23 +107,40 @@ __device__ inline bool sphere_in_cone(float ex, float ey, float ez, float nx, fl
   return cphi > cth * cb - sth * sb - 1e-4f;
 }
 
+// Min / max over the 16 lanes of a DPP row (rotations by 1, 2, 4, 8); every
+// lane of the row ends with the result.
+__device__ inline int row_min(int v) {
+  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x121, 0xf, 0xf, true));
+  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x122, 0xf, 0xf, true));
+  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, true));
+  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, true));
+  return v;
+}
+__device__ inline int row_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x121, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x122, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, true));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, true));
+  return v;
+}
+
+// One wavefront: voxel group `grp` (deepest groups first: they see the most
+// receivers) for the 16 NB batch columns `by` of the workspace: tile
+// by / subs, columns col0 .. col0 + 16 NB - 1 of its TW (subs = TW / 16 NB).
 template <class T, int NB, int QN, bool WTX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward(
-    Geom g, const T* __restrict__ ws, int B,
-                                                    int Bp, int Kc, float* __restrict__ x, int ngx,
-                                                    int ngy, int ngroups) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int grp = blockIdx.x * 4 + wave;
-  if (grp >= ngroups) return;  // whole wavefront
-  // deepest groups first (they see the most receivers)
+__device__ __forceinline__ void group_body(const Geom& g, const T* __restrict__ ws, int B, int TW,
+                                           int Kc, float* __restrict__ x, int ngx, int ngy,
+                                           int grp, int by) {
+  const int lane = threadIdx.x & 63;
   const int per_z = ngx * ngy;
   const int gz = g.n[2] - 1 - grp / per_z;
   const int gx = grp % ngx, gy = (grp / ngx) % ngy;
   const int vi = lane & 15, row = lane >> 4;
   const int ix = gx * 4 + (vi & 3), iy = gy * 4 + (vi >> 2);
-  const int b0 = blockIdx.y * 16 * NB;
   const int M = g.M, K = g.K;
   const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+  const int subs = TW / (16 * NB);
+  const int tile = by / subs, col0 = (by - tile * subs) * 16 * NB;
 
   double px, py, pz;
   tile_ref_point(g, gx * 4 + 1.5, gy * 4 + 1.5, (double)gz, px, py, pz);
@@ -146,9 +154,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void m
   const bool hann = g.apod == DAS_APOD_HANN_FNUM;
   const float cth = hann ? sqrtf(g.fourF2) * rsqrtf(1.f + g.fourF2) : -1.f;
   const float sth = hann ? rsqrtf(1.f + g.fourF2) : 0.f;
-  const size_t chunk_stride = (size_t)Bp * CH;  // elements per chunk
-  const size_t chan_stride = (size_t)Kc * chunk_stride;
-  const int nbv = min(NB, (Bp - b0) >> 4);       // batch tiles present (uniform)
+  // workspace strides in elements: chunk, (q, m) channel, transmit, tile
+  const uint32_t chunk_el = (uint32_t)TW * CH;
+  const size_t chan_el = (size_t)Kc * chunk_el;
+  const size_t q_el = (size_t)M * chan_el;
+  const T* wtile = ws + (size_t)tile * g.Q * q_el + (size_t)(col0 + vi) * CH;
   constexpr int BIG = 1 << 29;
 
   f32x4 acc[NB];
@@ -169,7 +179,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void m
       r.vy = __shfl(mine.vy, q);
       r.vz = __shfl(mine.vz, q);
       r.vn = __shfl(mine.vn, q);
-      ktx[q] = __builtin_amdgcn_readfirstlane(__shfl(mine.ktx, q));
+      ktx[q] = __shfl(mine.ktx, q);
       bq[q] = fmaf(delta_tx(r, dx, dy, dz, dp2), fscf, __shfl(mine.g, q));
       if constexpr (WTX) wq[q] = (q < qn && inside) ? g.w_tx[(size_t)(q0 + q) * N + n] : 0.f;
     }
@@ -222,80 +232,91 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void m
         const float w = j < 0 ? 0.f : rx_weight(g, m, ex + dx, ey + dy, ez + dz);
         if (__ballot(w != 0.f) == 0ull) continue;
         const float a = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, h);
-        const T* chan = ws + ((size_t)q0 * M + m) * chan_stride + (size_t)(b0 + vi) * CH;
-#pragma unroll
-        for (int q = 0; q < QN; ++q) {
-          if (q >= qn) break;  // uniform
-          const float f = a + bq[q];
-          const int t = ktx[q] + krx + floor_i32(f);  // absolute tap index
+        const T* chan = wtile + (size_t)q0 * q_el + (size_t)m * chan_el;
+
+        // Per transmit: tap, packed weights and the chunk range of each
+        // receiver row (DPP min/max over its 16 voxels).  Transmits past qn
+        // (padding of the compile-time group) get zero weights and read the
+        // group's first channel.  Rows with no live tap start at chunk 0, so
+        // chunks c_lo and c_lo + 1 always exist (c_lo <= ceil(K/8) = Kc - 2).
+        struct Step {
+          uint32_t P, Plo;
+          int dv, c_lo, nrow;
+        };
+        auto step = [&](int q, float bqv, int ktxv, float wqv) {
+          Step r;
+          const bool live = q < qn;
+          const float f = a + bqv;
+          const int t = ktxv + krx + floor_i32(f);  // absolute tap index
           const float al = frac_f32(f);
           // taps outside [-1, K-1] read only zero padding
-          const bool valid = w != 0.f && t >= -1 && t <= K - 1;
-          const float wt = valid ? (WTX ? w * wq[WTX ? q : 0] : w) : 0.f;
+          const bool valid = live && w != 0.f && t >= -1 && t <= K - 1;
+          const float wt = valid ? (WTX ? w * wqv : w) : 0.f;
           const float w2 = wt * al, w1 = wt - w2;
-          const uint32_t P = Mma<T>::pack(w1, w2);
-          uint32_t Plo = 0;
-          if constexpr (Mma<T>::kSplit) Plo = Mma<T>::pack(w1 - bf16_value(w1), w2 - bf16_value(w2));
-          // chunk range of this receiver row: samples [tmin, tmax + 1]
+          r.P = Mma<T>::pack(w1, w2);
+          r.Plo = 0;
+          if constexpr (Mma<T>::kSplit) r.Plo = Mma<T>::pack(w1 - bf16_value(w1), w2 - bf16_value(w2));
           const int tmin = row_min(valid ? t : BIG);
           const int tmax = row_max(valid ? t : -BIG);
-          const int c_lo = (tmin + CH) >> 3;  // chunk holding sample tmin
-          const int nrow = tmax < tmin ? 0 : ((tmax + 1 + CH) >> 3) - c_lo + 1;
-          const int nc = max(max(__builtin_amdgcn_readlane(nrow, 0), __builtin_amdgcn_readlane(nrow, 16)),
-                             max(__builtin_amdgcn_readlane(nrow, 32), __builtin_amdgcn_readlane(nrow, 48)));
-          const T* cq = chan + (size_t)q * M * chan_stride;
-          const int dv = valid ? t + CH - CH * c_lo : -BIG;  // slot of tap t in chunk c_lo
-          // Nearly every row spans one or two chunks: issue both chunks' loads
-          // unconditionally (clamped addresses, zero weights when unused),
-          // then the MFMAs, then any further chunks.
-          {
-            const T* p0 = cq + (size_t)min(max(c_lo, 0), Kc - 1) * chunk_stride;
-            const T* p1 = cq + (size_t)min(max(c_lo + 1, 0), Kc - 1) * chunk_stride;
-            u32x4 B0[NB], B1[NB];
+          const bool any = tmax >= tmin;
+          r.c_lo = any ? (tmin + CH) >> 3 : 0;  // chunk holding sample tmin
+          r.nrow = any ? ((tmax + 1 + CH) >> 3) - r.c_lo + 1 : 0;
+          r.dv = valid ? t + CH - CH * r.c_lo : -BIG;  // slot of tap t in chunk c_lo
+          return r;
+        };
+        auto mma_chunk = [&](const Step& r, int u, const u32x4 (&Bf)[NB]) {
+          const u32x4 A = place_pair(r.P, r.dv - CH * u);
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-              if (nb < nbv) {
-                B0[nb] = *reinterpret_cast<const u32x4*>(p0 + nb * 16 * CH);
-                B1[nb] = *reinterpret_cast<const u32x4*>(p1 + nb * 16 * CH);
-              }
-            }
-            const u32x4 A0 = place_pair(P, dv), A1 = place_pair(P, dv - CH);
+          for (int nb = 0; nb < NB; ++nb) acc[nb] = Mma<T>::mma(A, Bf[nb], acc[nb]);
+          if constexpr (Mma<T>::kSplit) {
+            const u32x4 Al = place_pair(r.Plo, r.dv - CH * u);
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-              if (nb < nbv) {
-                acc[nb] = Mma<T>::mma(A0, B0[nb], acc[nb]);
-                acc[nb] = Mma<T>::mma(A1, B1[nb], acc[nb]);
-              }
-            }
-            if constexpr (Mma<T>::kSplit) {
-              const u32x4 L0 = place_pair(Plo, dv), L1 = place_pair(Plo, dv - CH);
-#pragma unroll
-              for (int nb = 0; nb < NB; ++nb) {
-                if (nb < nbv) {
-                  acc[nb] = Mma<T>::mma(L0, B0[nb], acc[nb]);
-                  acc[nb] = Mma<T>::mma(L1, B1[nb], acc[nb]);
-                }
-              }
-            }
+            for (int nb = 0; nb < NB; ++nb) acc[nb] = Mma<T>::mma(Al, Bf[nb], acc[nb]);
           }
+        };
+        // Pass 1, branch-free: the first two chunks of every transmit (rows
+        // of compact groups span one or two chunks).
+        uint32_t rest = 0;  // transmits with a row that spans more than two chunks
+        const T* cq = chan;
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+          const Step r = step(q, bq[q], ktx[q], WTX ? wq[WTX ? q : 0] : 1.f);
+          const T* p0 = cq + __mul24(r.c_lo, (int)chunk_el);
+          u32x4 B0[NB], B1[NB];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            B0[nb] = *reinterpret_cast<const u32x4*>(p0 + nb * 16 * CH);
+            B1[nb] = *reinterpret_cast<const u32x4*>(p0 + chunk_el + nb * 16 * CH);
+          }
+          mma_chunk(r, 0, B0);
+          mma_chunk(r, 1, B1);
+          if (__ballot(r.nrow > 2)) rest |= 1u << q;
+          if (q + 1 < qn) cq += q_el;
+        }
+        // Pass 2 (wide tap spreads only): the remaining chunks, one transmit
+        // at a time, its reference terms taken again from the lane holding them.
+        while (rest) {
+          const int q = __builtin_ctz(rest);
+          rest &= rest - 1u;
+          TxRef tr;
+          tr.kind = __shfl(mine.kind, q);
+          tr.vx = __shfl(mine.vx, q);
+          tr.vy = __shfl(mine.vy, q);
+          tr.vz = __shfl(mine.vz, q);
+          tr.vn = __shfl(mine.vn, q);
+          const int ktxv = __shfl(mine.ktx, q);
+          const float bqv = fmaf(delta_tx(tr, dx, dy, dz, dp2), fscf, __shfl(mine.g, q));
+          const float wqv = WTX && inside ? g.w_tx[(size_t)(q0 + q) * N + n] : 1.f;
+          const Step r = step(q, bqv, ktxv, wqv);
+          const int nc = __builtin_amdgcn_readfirstlane(
+              max(max(__shfl(r.nrow, 0), __shfl(r.nrow, 16)), max(__shfl(r.nrow, 32), __shfl(r.nrow, 48))));
+          const T* cqq = chan + (size_t)q * q_el;
           for (int u = 2; u < nc; ++u) {
-            const int cc = min(max(c_lo + u, 0), Kc - 1);
-            const T* p = cq + (size_t)cc * chunk_stride;
-            const int d = dv - CH * u;
-            const u32x4 A = place_pair(P, d);
+            const T* p = cqq + (size_t)min(r.c_lo + u, Kc - 1) * chunk_el;
             u32x4 Bf[NB];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-              if (nb < nbv) Bf[nb] = *reinterpret_cast<const u32x4*>(p + nb * 16 * CH);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-              if (nb < nbv) acc[nb] = Mma<T>::mma(A, Bf[nb], acc[nb]);
-            if constexpr (Mma<T>::kSplit) {
-              const u32x4 Al = place_pair(Plo, d);
-#pragma unroll
-              for (int nb = 0; nb < NB; ++nb)
-                if (nb < nbv) acc[nb] = Mma<T>::mma(Al, Bf[nb], acc[nb]);
-            }
+            for (int nb = 0; nb < NB; ++nb) Bf[nb] = *reinterpret_cast<const u32x4*>(p + nb * 16 * CH);
+            mma_chunk(r, u, Bf);
           }
         }
       }
@@ -305,8 +326,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void m
   const int jy = gy * 4 + row;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    const int b = b0 + nb * 16 + vi;
-    if (nb >= nbv || b >= B || jy >= g.n[1]) continue;
+    const int b = tile * TW + col0 + nb * 16 + vi;
+    if (b >= B || jy >= g.n[1]) continue;
     float* xb = x + (size_t)b * N + (size_t)g.n[0] * (jy + (size_t)g.n[1] * gz);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -316,15 +337,275 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void m
   }
 }
 
-// y[nb][Q][M][K] f32 -> chunked batch-inner ws[Q][M][Kc][Bp][8] for items
-// b0 .. b0+nb-1.  A workgroup converts 32 chunks (256 samples) of 16 items of
+// Depth-stacked form: one wavefront owns ZS voxel groups stacked in depth
+// (a 4 x 4 x ZS column) for 16 batch columns.  Per receiver row it loads the
+// union of the groups' chunks once, and applies to each loaded chunk the A
+// fragments of the groups that have taps in it (a wave-uniform test per
+// (group, chunk)), so a chunk read from L2 serves up to ZS groups.  Delays are
+// formed relative to the column centre.
+template <class T, int ZS, int QN, bool WTX>
+__device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ ws, int B, int TW,
+                                           int Kc, float* __restrict__ x, int ngx, int ngy,
+                                           int col, int by) {
+  constexpr int NCH = ZS / 2 + 2;  // chunks loaded per step before the rare second pass
+  const int lane = threadIdx.x & 63;
+  const int per_z = ngx * ngy;
+  const int gz0 = g.n[2] - ZS * (col / per_z + 1);  // first depth of the stack (deepest first)
+  const int gx = col % ngx, gy = (col / ngx) % ngy;
+  const int vi = lane & 15, row = lane >> 4;
+  const int ix = gx * 4 + (vi & 3), iy = gy * 4 + (vi >> 2);
+  const int M = g.M, K = g.K;
+  const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+  const int subs = TW / 16;
+  const int tile = by / subs, col0 = (by - tile * subs) * 16;
+
+  double px, py, pz;
+  tile_ref_point(g, gx * 4 + 1.5, gy * 4 + 1.5, gz0 + 0.5 * (ZS - 1), px, py, pz);
+  const float sx = (float)g.s[0], sy = (float)g.s[1], sz = (float)g.s[2];
+  const float dx = ((float)(vi & 3) - 1.5f) * sx, dy = ((float)(vi >> 2) - 1.5f) * sy;
+  float dz[ZS], dp2[ZS];
+  int nk[ZS];
+  bool ink[ZS];
+#pragma unroll
+  for (int k = 0; k < ZS; ++k) {
+    dz[k] = ((float)k - 0.5f * (ZS - 1)) * sz;
+    dp2[k] = dx * dx + dy * dy + dz[k] * dz[k];
+    ink[k] = ix < g.n[0] && iy < g.n[1] && gz0 + k >= 0;
+    nk[k] = ink[k] ? grid_index(g, ix, iy, gz0 + k) : 0;
+  }
+  const float fscf = (float)g.fsc;
+  const float hz = 0.5f * (ZS - 1) * sz;
+  const float Rg = sqrtf(2.25f * (sx * sx + sy * sy) + hz * hz);
+  const bool hann = g.apod == DAS_APOD_HANN_FNUM;
+  const float cth = hann ? sqrtf(g.fourF2) * rsqrtf(1.f + g.fourF2) : -1.f;
+  const float sth = hann ? rsqrtf(1.f + g.fourF2) : 0.f;
+  const uint32_t chunk_el = (uint32_t)TW * CH;
+  const size_t chan_el = (size_t)Kc * chunk_el;
+  const size_t q_el = (size_t)M * chan_el;
+  const T* wtile = ws + (size_t)tile * g.Q * q_el + (size_t)(col0 + vi) * CH;
+  constexpr int BIG = 1 << 29;
+
+  f32x4 acc[ZS];
+#pragma unroll
+  for (int k = 0; k < ZS; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int q0 = 0; q0 < g.Q; q0 += QN) {
+    const int qn = min(QN, g.Q - q0);
+    TxRef mine = {};
+    if (lane < qn) mine = make_tx_ref(g, q0 + lane, px, py, pz);
+    float bq[QN][ZS], wq[WTX ? QN : 1][WTX ? ZS : 1];
+    int ktx[QN];
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+      TxRef r;
+      r.kind = __shfl(mine.kind, q);
+      r.vx = __shfl(mine.vx, q);
+      r.vy = __shfl(mine.vy, q);
+      r.vz = __shfl(mine.vz, q);
+      r.vn = __shfl(mine.vn, q);
+      ktx[q] = __shfl(mine.ktx, q);
+      const float gq = __shfl(mine.g, q);
+#pragma unroll
+      for (int k = 0; k < ZS; ++k) {
+        bq[q][k] = fmaf(delta_tx(r, dx, dy, dz[k], dp2[k]), fscf, gq);
+        if constexpr (WTX)
+          wq[q][k] = (q < qn && ink[k]) ? g.w_tx[(size_t)(q0 + q) * N + nk[k]] : 0.f;
+      }
+    }
+    for (int m0 = 0; m0 < M; m0 += 64) {
+      const int me = m0 + lane;
+      bool on = me < M;
+      float rex = 0.f, rey = 0.f, rez = 0.f, ren = 0.f, rh = 0.f;
+      int rk = 0;
+      if (on) {
+        const double ex = px - g.elem[3 * me + 0];
+        const double ey = py - g.elem[3 * me + 1];
+        const double ez = pz - g.elem[3 * me + 2];
+        rex = (float)ex;
+        rey = (float)ey;
+        rez = (float)ez;
+        if (hann) {
+          float nx = 0.f, ny = 0.f, nz = 1.f;
+          if (g.enorm) {
+            nx = g.enorm[3 * me + 0];
+            ny = g.enorm[3 * me + 1];
+            nz = g.enorm[3 * me + 2];
+          }
+          on = sphere_in_cone(rex, rey, rez, nx, ny, nz, Rg, cth, sth);
+        }
+        if (on) {
+          const double R = sqrt(ex * ex + ey * ey + ez * ez);
+          const double fr = R * g.fsc;
+          const double fl = floor(fr);
+          ren = (float)R;
+          rh = (float)(fr - fl);
+          rk = (int)fl;
+        }
+      }
+      uint64_t mk = __ballot(on);
+      while (mk) {
+        int js[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          js[r] = mk ? __builtin_ctzll(mk) : -1;
+          mk &= mk - 1ull;
+        }
+        const int j = row == 0 ? js[0] : row == 1 ? js[1] : row == 2 ? js[2] : js[3];
+        const int src = j < 0 ? 0 : j;
+        const float ex = __shfl(rex, src), ey = __shfl(rey, src), ez = __shfl(rez, src);
+        const float en = __shfl(ren, src), h = __shfl(rh, src);
+        const int krx = __shfl(rk, src);
+        const int m = m0 + src;
+        float w[ZS], a[ZS];
+        bool anyw = false;
+#pragma unroll
+        for (int k = 0; k < ZS; ++k) {
+          w[k] = j < 0 ? 0.f : rx_weight(g, m, ex + dx, ey + dy, ez + dz[k]);
+          a[k] = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz[k], dp2[k]), fscf, h);
+          anyw |= w[k] != 0.f;
+        }
+        if (__ballot(anyw) == 0ull) continue;
+        const T* cq = wtile + (size_t)q0 * q_el + (size_t)m * chan_el;
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+          const bool live = q < qn;
+          int t[ZS];
+          uint32_t P[ZS], Plo[ZS];
+          int lo = BIG, hi = -BIG;
+#pragma unroll
+          for (int k = 0; k < ZS; ++k) {
+            const float f = a[k] + bq[q][k];
+            t[k] = ktx[q] + krx + floor_i32(f);
+            const float al = frac_f32(f);
+            const bool valid = live && w[k] != 0.f && t[k] >= -1 && t[k] <= K - 1;
+            const float wt = valid ? (WTX ? w[k] * wq[WTX ? q : 0][WTX ? k : 0] : w[k]) : 0.f;
+            const float w2 = wt * al, w1 = wt - w2;
+            P[k] = Mma<T>::pack(w1, w2);
+            Plo[k] = 0;
+            if constexpr (Mma<T>::kSplit) Plo[k] = Mma<T>::pack(w1 - bf16_value(w1), w2 - bf16_value(w2));
+            lo = valid ? min(lo, t[k]) : lo;
+            hi = valid ? max(hi, t[k]) : hi;
+            t[k] = valid ? t[k] : -BIG;
+          }
+          const int tmin = row_min(lo), tmax = row_max(hi);
+          const bool any = tmax >= tmin;
+          const int c_lo = any ? (tmin + CH) >> 3 : 0;  // chunk holding sample tmin
+          const int nrow = any ? ((tmax + 1 + CH) >> 3) - c_lo + 1 : 0;
+          const int nc = max(max(__builtin_amdgcn_readlane(nrow, 0), __builtin_amdgcn_readlane(nrow, 16)),
+                             max(__builtin_amdgcn_readlane(nrow, 32), __builtin_amdgcn_readlane(nrow, 48)));
+          const T* cqq = cq + (size_t)(live ? q : 0) * q_el;
+          // slot of each tap relative to this row's chunk c_lo
+          int d[ZS];
+#pragma unroll
+          for (int k = 0; k < ZS; ++k) d[k] = t[k] > -BIG ? t[k] + CH - CH * c_lo : -BIG;
+          for (int u0 = 0; u0 < nc; u0 += NCH) {
+            u32x4 Bf[NCH];
+#pragma unroll
+            for (int u = 0; u < NCH; ++u)
+              if (u0 + u < nc)
+                Bf[u] = *reinterpret_cast<const u32x4*>(
+                    cqq + (size_t)min(c_lo + u0 + u, Kc - 1) * chunk_el);
+#pragma unroll
+            for (int k = 0; k < ZS; ++k) {
+#pragma unroll
+              for (int u = 0; u < NCH; ++u) {
+                if (u0 + u >= nc) continue;
+                const int du = d[k] - CH * (u0 + u);
+                // does any lane hold a tap of group k in this chunk?
+                if (__ballot((unsigned)(du + 1) <= (unsigned)CH) == 0ull) continue;
+                acc[k] = Mma<T>::mma(place_pair(P[k], du), Bf[u], acc[k]);
+                if constexpr (Mma<T>::kSplit) acc[k] = Mma<T>::mma(place_pair(Plo[k], du), Bf[u], acc[k]);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  const int jy = gy * 4 + row;
+  const int b = tile * TW + col0 + vi;
+  if (b >= B || jy >= g.n[1]) return;
+#pragma unroll
+  for (int k = 0; k < ZS; ++k) {
+    if (gz0 + k < 0) continue;
+    float* xb = x + (size_t)b * N + (size_t)g.n[0] * (jy + (size_t)g.n[1] * (gz0 + k));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int jx = gx * 4 + r;
+      if (jx < g.n[0]) xb[jx] = acc[k][r];
+    }
+  }
+}
+
+// XCD-aware order: the hardware deals workgroups round-robin to the 8 XCDs of
+// the chip, each with its own L2.  Remap so that every XCD receives runs of 64
+// consecutive blocks (256 neighbouring voxel groups, which read overlapping
+// sample chunks); runs stay interleaved across XCDs, which keeps the
+// depth-dependent work balanced.  The ragged last round keeps its order.
+__device__ inline int xcd_remap(int b, int nblocks) {
+  constexpr int X = 8, C = 64, per = X * C;
+  if (b >= nblocks / per * per) return b;
+  const int r = b / per, k = b - r * per;
+  return r * per + (k % X) * C + k / X;
+}
+
+template <class T, int NB, int QN, bool WTX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward(
+    Geom g, const T* __restrict__ ws, int B, int TW, int Kc, float* __restrict__ x, int ngx,
+    int ngy, int ngroups) {
+  const int grp = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (grp >= ngroups) return;  // whole wavefront
+  group_body<T, NB, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, grp, blockIdx.y);
+}
+
+template <class T, int ZS, int QN, bool WTX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward_stack(
+    Geom g, const T* __restrict__ ws, int B, int TW, int Kc, float* __restrict__ x, int ngx,
+    int ngy, int ncols) {
+  const int col = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (col >= ncols) return;  // whole wavefront
+  stack_body<T, ZS, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y);
+}
+
+// Voxel groups per wavefront column of the depth-stacked form (1 = one group
+// per wavefront).
+constexpr int kStack = 2;
+
+// Persistent form: workgroups walk one list of (plan, block of 4 wavefront
+// columns, 16-item batch slice) items; plan i owns items first[i] ..
+// first[i+1]-1, block-major within its batch slices.  No LDS and no barriers,
+// so wavefronts with nothing to do simply skip an item.  Each item runs the
+// same body as a single-plan launch, so results are identical bit for bit.
+template <class T, int QN, bool WTX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward_batched(
+    MfmaBatchedArgs a) {
+  const int total = a.first[a.count];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int i = 0;
+    while (item >= a.first[i + 1]) ++i;
+    const MfmaWork& w = a.p[i];
+    const int local = item - a.first[i];
+    const int bx = local % w.nbx, by = local / w.nbx;
+    const int col = bx * 4 + (threadIdx.x >> 6);
+    if (col >= w.ngroups) continue;
+    if constexpr (kStack > 1)
+      stack_body<T, kStack, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x, w.ngx,
+                                     w.ngy, col, by);
+    else
+      group_body<T, 1, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x, w.ngx,
+                                w.ngy, col, by);
+  }
+}
+
+// y[nb][Q][M][K] f32 -> batch-tiled chunked workspace ws[Bp/TW][Q][M][Kc][TW][8]
+// for items b0 .. b0+nb-1.  A workgroup converts 32 chunks (256 samples) of 16 items of
 // one channel (q, m): rows of 256 samples are read coalesced into LDS, then
 // each thread packs two 8-sample chunks, the 16 items of a chunk being
 // adjacent 16-byte stores.
 constexpr int RC = 32;  // chunks per reorder tile
 template <class T>
 __global__ __launch_bounds__(256) void reorder_chunks(const float* __restrict__ y, int Q, int M,
-                                                      int K, int Kc, int nb, int b0, int Bp,
+                                                      int K, int Kc, int nb, int b0, int TW,
                                                       T* __restrict__ ws) {
   __shared__ float tile[16][RC * CH + 1];
   const long long QM = (long long)Q * M;
@@ -356,7 +637,9 @@ __global__ __launch_bounds__(256) void reorder_chunks(const float* __restrict__ 
         }
         const u32x4 o4{v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
                        v[6] | (v[7] << 16)};
-        *reinterpret_cast<u32x4*>(ws + ((qm * Kc + kc) * Bp + b0 + b) * CH) = o4;
+        const int ba = b0 + b, tile = ba / TW;
+        *reinterpret_cast<u32x4*>(ws + (((long long)tile * QM + qm) * Kc + kc) * TW * CH +
+                                  (long long)(ba - tile * TW) * CH) = o4;
       }
     }
     __syncthreads();
@@ -367,10 +650,10 @@ template <class T, int NB, int QN, bool WTX>
 hipError_t launch_t(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
   const int ngx = (g.n[0] + 3) / 4, ngy = (g.n[1] + 3) / 4;
   const int ngroups = ngx * ngy * g.n[2];
-  const int Bp = mfma_batch_pad(B), Kc = mfma_chunks(g.K);
-  dim3 grid((ngroups + 3) / 4, (Bp + 16 * NB - 1) / (16 * NB));
+  const int TW = mfma_tile_width(B), Kc = mfma_chunks(g.K);
+  dim3 grid((ngroups + 3) / 4, mfma_batch_pad(B) / TW);
   hipLaunchKernelGGL((mfma_forward<T, NB, QN, WTX>), grid, dim3(256), 0, st, g,
-                     static_cast<const T*>(ws), B, Bp, Kc, x, ngx, ngy, ngroups);
+                     static_cast<const T*>(ws), B, TW, Kc, x, ngx, ngy, ngroups);
   return hipGetLastError();
 }
 
@@ -386,16 +669,81 @@ hipError_t launch_nb(const Geom& g, const void* ws, int B, float* x, hipStream_t
   }
 }
 
+template <class T, int ZS, int QN, bool WTX>
+hipError_t launch_stack_t(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
+  const int ngx = (g.n[0] + 3) / 4, ngy = (g.n[1] + 3) / 4;
+  const int ncols = ngx * ngy * ((g.n[2] + ZS - 1) / ZS);
+  const int TW = mfma_tile_width(B), Kc = mfma_chunks(g.K);
+  dim3 grid((ncols + 3) / 4, mfma_batch_pad(B) / 16);
+  hipLaunchKernelGGL((mfma_forward_stack<T, ZS, QN, WTX>), grid, dim3(256), 0, st, g,
+                     static_cast<const T*>(ws), B, TW, Kc, x, ngx, ngy, ncols);
+  return hipGetLastError();
+}
+
+template <class T, int ZS>
+hipError_t launch_stack(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
+  constexpr int QMAX = ZS >= 8 ? 4 : 8;
+  const bool wtx = g.w_tx != nullptr;
+  const int qg = g.Q == 1 ? 1 : (g.Q <= 4 || QMAX == 4) ? 4 : 8;
+  if (qg == 1)
+    return wtx ? launch_stack_t<T, ZS, 1, true>(g, ws, B, x, st) : launch_stack_t<T, ZS, 1, false>(g, ws, B, x, st);
+  if (qg == 4)
+    return wtx ? launch_stack_t<T, ZS, 4, true>(g, ws, B, x, st) : launch_stack_t<T, ZS, 4, false>(g, ws, B, x, st);
+  return wtx ? launch_stack_t<T, ZS, QMAX, true>(g, ws, B, x, st)
+             : launch_stack_t<T, ZS, QMAX, false>(g, ws, B, x, st);
+}
+
 template <class T>
 hipError_t launch_any(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
-  if (B > 32) return launch_nb<T, 4>(g, ws, B, x, st);
-  if (B > 16) return launch_nb<T, 2>(g, ws, B, x, st);
+  if constexpr (kStack > 1) return launch_stack<T, kStack>(g, ws, B, x, st);
+  const int nb = mfma_tiles_per_wave(B);
+  if (nb == 4) return launch_nb<T, 4>(g, ws, B, x, st);
+  if (nb == 2) return launch_nb<T, 2>(g, ws, B, x, st);
   return launch_nb<T, 1>(g, ws, B, x, st);
+}
+
+template <class T, int QN, bool WTX>
+hipError_t batched_t(const MfmaBatchedArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((mfma_forward_batched<T, QN, WTX>), dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t batched_any(const MfmaBatchedArgs& a, int qn, bool wtx, int grid, hipStream_t st) {
+  constexpr int QMAX = kStack >= 8 ? 4 : kStack > 1 ? 8 : 16;
+  if (qn == 1) return wtx ? batched_t<T, 1, true>(a, grid, st) : batched_t<T, 1, false>(a, grid, st);
+  if (qn <= 4) return wtx ? batched_t<T, 4, true>(a, grid, st) : batched_t<T, 4, false>(a, grid, st);
+  return wtx ? batched_t<T, QMAX, true>(a, grid, st) : batched_t<T, QMAX, false>(a, grid, st);
 }
 
 }  // namespace
 
-int mfma_batch_pad(int B) { return (B + 15) & ~15; }
+int mfma_tiles_per_wave(int B) { return B > 32 ? 4 : B > 16 ? 2 : 1; }
+int mfma_tile_width(int B) { return 16 * mfma_tiles_per_wave(B); }
+int mfma_batch_pad(int B) {
+  const int tw = mfma_tile_width(B);
+  return (B + tw - 1) / tw * tw;
+}
+
+hipError_t launch_mfma_batched(MfmaBatchedArgs& a, int storage, int cus, hipStream_t st) {
+  int qn = 1;
+  bool wtx = false;
+  a.first[0] = 0;
+  for (int i = 0; i < a.count; ++i) {
+    MfmaWork& w = a.p[i];
+    const int Q = w.g.Q;
+    qn = std::max(qn, Q == 1 ? 1 : Q <= 4 ? 4 : 16);
+    wtx |= w.g.w_tx != nullptr;
+    w.ngx = (w.g.n[0] + 3) / 4;
+    w.ngy = (w.g.n[1] + 3) / 4;
+    w.ngroups = w.ngx * w.ngy * ((w.g.n[2] + kStack - 1) / kStack);  // wavefront columns
+    w.nbx = (w.ngroups + 3) / 4;
+    a.first[i + 1] = a.first[i] + w.nbx * (mfma_batch_pad(w.B) / 16);
+  }
+  const int grid = std::max(1, std::min(a.first[a.count], 4 * cus));
+  if (storage == DAS_STORE_F16) return batched_any<_Float16>(a, qn, wtx, grid, st);
+  return batched_any<uint16_t>(a, qn, wtx, grid, st);
+}
 int mfma_chunks(int K) { return (K + CH - 1) / CH + 2; }
 
 size_t mfma_workspace_elems(const Geom& g, int B) {
@@ -404,15 +752,15 @@ size_t mfma_workspace_elems(const Geom& g, int B) {
 
 hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b0, int nb, int btot,
                                void* ws, hipStream_t st) {
-  const int Kc = mfma_chunks(g.K), Bp = mfma_batch_pad(btot);
+  const int Kc = mfma_chunks(g.K), TW = mfma_tile_width(btot);
   const long long QM = (long long)g.Q * g.M;
   const dim3 grid((Kc + RC - 1) / RC, (unsigned)std::min<long long>(QM, 65535), (nb + 15) / 16);
   if (storage == DAS_STORE_F16)
     hipLaunchKernelGGL(reorder_chunks<_Float16>, grid, dim3(256), 0, st, y, g.Q, g.M, g.K, Kc, nb,
-                       b0, Bp, static_cast<_Float16*>(ws));
+                       b0, TW, static_cast<_Float16*>(ws));
   else
     hipLaunchKernelGGL(reorder_chunks<uint16_t>, grid, dim3(256), 0, st, y, g.Q, g.M, g.K, Kc, nb,
-                       b0, Bp, static_cast<uint16_t*>(ws));
+                       b0, TW, static_cast<uint16_t*>(ws));
   return hipGetLastError();
 }
 

@@ -24,8 +24,8 @@ def _block_around(g, pos, half=8):
     return synth.sub_grid(g, start, (2 * half, 2 * half, 2 * half))
 
 
-@pytest.mark.parametrize("storage,max_db,mean_db", [("f32", 0.01, 0.001), ("f16", 1.0, 0.05),
-                                                    ("bf16", 3.0, 0.3)])
+@pytest.mark.parametrize("storage,max_db,mean_db", [("f32", 0.002, 0.0002), ("f16", 0.05, 0.005),
+                                                    ("bf16", 0.4, 0.04)])
 def test_envelope_and_point_targets_cfg2(gpu, storage, max_db, mean_db):
     """Envelope-dB error (voxels within 40 dB of the peak) and point-target
     peak / -6 dB widths of the precision forms vs the oracle, on a 16^3 block
@@ -52,27 +52,23 @@ def test_envelope_and_point_targets_cfg2(gpu, storage, max_db, mean_db):
 
 
 def test_autofocus_converges_to_scan_argmax(gpu):
-    """cfg5 (data made at 1500 m/s), starting at 1540 m/s: the gradient loop on
-    the GPU converges to the argmax of a brute-force scan of the oracle's
-    envelope energy over [1480, 1560] m/s (0.5 m/s resolution)."""
+    """cfg5 (data simulated at 1500 m/s on the CPU), loss = envelope energy of
+    the full 64^3 volume, gradient loop from 1540 m/s bounded to [1480, 1560]:
+    it converges to the argmax of the oracle's brute-force scan of the same
+    loss over that range (tests/golden/autofocus_scan.json, written by
+    tests/golden/make_autofocus_scan.py from the oracle alone).  How close
+    that argmax is to 1500 m/s is reported, not asserted: on this geometry the
+    energy of a fixed voxel grid grows with the assumed speed."""
+    import json
+    import os
     from paper_2606_13259_amd import autofocus
     das = _das()
-    g, s, y = synth.cfg5_data(device="cuda:0")
-    tgt = s.pos[int(np.argmax(s.amp[:50]))]
-    sub = _block_around(g, tgt, half=5)
-    yc = y.cpu().numpy()
-    lanes_o = oenv.analytic_lanes(yc)
-
-    def L(c):
-        x = oracle.forward(lanes_o, sub, c=c)
-        return float(np.sum(x ** 2))
-
-    coarse = np.arange(1480.0, 1560.0 + 1e-9, 2.0)
-    lc = [L(c) for c in coarse]
-    c1 = coarse[int(np.argmax(lc))]
-    fine = np.arange(c1 - 2.0, c1 + 2.0 + 1e-9, 0.5)
-    c_best = fine[int(np.argmax([L(c) for c in fine]))]
-    plan = das.Plan(sub, max_batch=2, storage="f32")
-    c_gpu, hist = autofocus.autofocus(plan, y, c0=1540.0)
-    say(f"  scan argmax {c_best:.1f} m/s; autofocus {c_gpu:.2f} m/s after {len(hist)} steps")
+    with open(os.path.join(os.path.dirname(__file__), "golden", "autofocus_scan.json")) as f:
+        scan = json.load(f)
+    c_best = scan["argmax_c"]
+    g, s, y = synth.cfg5_data(device="cpu")
+    plan = das.Plan(g, max_batch=2, storage="f32")
+    c_gpu, hist = autofocus.autofocus(plan, y.to(gpu), c0=1540.0, bounds=(1480.0, 1560.0))
+    say(f"  oracle scan argmax {c_best:.1f} m/s; autofocus {c_gpu:.2f} m/s after {len(hist)} steps "
+        f"(data speed 1500 m/s)")
     assert abs(c_gpu - c_best) <= 0.5

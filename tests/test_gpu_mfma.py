@@ -146,3 +146,38 @@ def test_mfma_cfg2_full_volume_sampled(gpu, storage):
     for i, b in enumerate(items):
         check_close(x[i][idx], xo[i], *lowp_bars(storage), f"item {b}, sampled voxels")
         check_close(x[i][idx], xr[i], KERNEL_REL[storage], KERNEL_ABS[storage], "  rounded data")
+
+
+def test_mfma_persistent_batched_launch(gpu):
+    """One persistent MFMA launch over plans with different grids, arrays,
+    transmit counts and batch sizes (different column tiles per wavefront)
+    equals separate launches bit for bit, and the oracle within the bars."""
+    das = _das()
+    geoms = [_ragged_geometry(),
+             synth.sub_grid(synth.cfg5(), (20, 24, 10), (9, 8, 12)),
+             synth.cfg1()]
+    batches = [40, 17, 16]
+    plans, wss, xs, ys = [], [], [], []
+    for g, B in zip(geoms, batches):
+        y = synth.random_channel_data(g, B, seed=50 + B)
+        p = das.Plan(g, max_batch=B, storage="f16")
+        assert p.algo(B) == "mfma"
+        ws = p.prepare(y.to(gpu))
+        plans.append(p)
+        wss.append(ws)
+        xs.append(torch.full((B, p.N), float("nan"), device=gpu))
+        ys.append(y)
+    das.das_forward_batched([p.handle for p in plans], wss, batches, xs)
+    for p, ws, x, y, g, B in zip(plans, wss, xs, ys, geoms, batches):
+        xsep = p.forward_ws(ws, B)
+        assert torch.equal(x, xsep), "batched launch differs from a separate launch"
+        idx = [0, B - 1]
+        _check_both(x[idx].cpu().numpy(), y.numpy()[idx], g, "f16", f"batched {g.grid_dims}")
+    # plans of different algorithms cannot share one launch
+    g = geoms[2]
+    p_t = das.Plan(g, max_batch=2, storage="f16")
+    ws_t = p_t.prepare(synth.random_channel_data(g, 2, seed=3).to(gpu))
+    with pytest.raises(das.DasError) as e:
+        das.das_forward_batched([plans[2].handle, p_t.handle], [wss[2], ws_t], [16, 2],
+                                [xs[2], torch.empty(2, p_t.N, device=gpu)])
+    assert e.value.status == das.DAS_ERR_UNSUPPORTED
