@@ -565,11 +565,10 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plans[0]->device);
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-  const int grid = std::max(1, std::min(a.first[count], 3 * cus));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (storage == DAS_STORE_F32) e = tiled_batched_f32(a, bt, qn, wtx, grid, st);
-  else if (storage == DAS_STORE_F16) e = tiled_batched_f16(a, bt, qn, wtx, grid, st);
-  else e = tiled_batched_bf16(a, bt, qn, wtx, grid, st);
+  if (storage == DAS_STORE_F32) e = tiled_batched_f32(a, bt, qn, wtx, cus, st);
+  else if (storage == DAS_STORE_F16) e = tiled_batched_f16(a, bt, qn, wtx, cus, st);
+  else e = tiled_batched_bf16(a, bt, qn, wtx, cus, st);
   if (e != hipSuccess) return hip_fail(e, "das_forward_batched launch");
   return DAS_OK;
 }

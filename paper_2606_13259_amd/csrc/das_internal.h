@@ -56,11 +56,11 @@ struct BatchedArgs {
   int first[MAX_BATCHED + 1];  // work-item ranges per plan
   int count;
 };
-hipError_t tiled_batched_f32(const BatchedArgs& a, int bt, int qn, bool wtx, int grid,
+hipError_t tiled_batched_f32(const BatchedArgs& a, int bt, int qn, bool wtx, int cus,
                              hipStream_t st);
-hipError_t tiled_batched_f16(const BatchedArgs& a, int bt, int qn, bool wtx, int grid,
+hipError_t tiled_batched_f16(const BatchedArgs& a, int bt, int qn, bool wtx, int cus,
                              hipStream_t st);
-hipError_t tiled_batched_bf16(const BatchedArgs& a, int bt, int qn, bool wtx, int grid,
+hipError_t tiled_batched_bf16(const BatchedArgs& a, int bt, int qn, bool wtx, int cus,
                               hipStream_t st);
 
 // ---------------------------------------------------------------------------

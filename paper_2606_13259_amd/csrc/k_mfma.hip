@@ -538,12 +538,12 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
 }
 
 // XCD-aware order: the hardware deals workgroups round-robin to the 8 XCDs of
-// the chip, each with its own L2.  Remap so that every XCD receives runs of 64
-// consecutive blocks (256 neighbouring voxel groups, which read overlapping
-// sample chunks); runs stay interleaved across XCDs, which keeps the
-// depth-dependent work balanced.  The ragged last round keeps its order.
+// the chip, each with its own L2.  Remap so that every XCD receives runs of 128
+// consecutive blocks (512 neighbouring wavefront columns, which read
+// overlapping sample chunks); runs stay interleaved across XCDs, which keeps
+// the depth-dependent work balanced.  The ragged last round keeps its order.
 __device__ inline int xcd_remap(int b, int nblocks) {
-  constexpr int X = 8, C = 64, per = X * C;
+  constexpr int X = 8, C = 128, per = X * C;
   if (b >= nblocks / per * per) return b;
   const int r = b / per, k = b - r * per;
   return r * per + (k % X) * C + k / X;
@@ -580,10 +580,23 @@ template <class T, int QN, bool WTX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward_batched(
     MfmaBatchedArgs a) {
   const int total = a.first[a.count];
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+  const unsigned G = gridDim.x;
+  for (int r = 0; r * (int)G < total; ++r) {
+    // Round r covers list positions r G .. r G + G - 1.  The slot of this
+    // block rotates by 104 per round: a static slot would give a block the
+    // same lateral position in every round (rounds span whole depth slices)
+    // and leave the launch waiting on the blocks of the array's centre.  The
+    // rotation is a multiple of 8 and G is a multiple of 8 (or covers the
+    // whole list), so v stays on this block's XCD and the remap hands each
+    // XCD runs of neighbouring items.
+    const int v = r * (int)G + (int)((blockIdx.x + 104u * (unsigned)r) % G);
+    if (v >= total) continue;
+    const int item = G % 8 == 0 ? xcd_remap(v, total) : v;
     int i = 0;
     while (item >= a.first[i + 1]) ++i;
-    const MfmaWork& w = a.p[i];
+    // copy the plan's share out of the argument block (uniform index: scalar
+    // loads once per item, not a memory access per use in the loops)
+    const MfmaWork w = a.p[i];
     const int local = item - a.first[i];
     const int bx = local % w.nbx, by = local / w.nbx;
     const int col = bx * 4 + (threadIdx.x >> 6);
@@ -703,17 +716,27 @@ hipError_t launch_any(const Geom& g, const void* ws, int B, float* x, hipStream_
 }
 
 template <class T, int QN, bool WTX>
-hipError_t batched_t(const MfmaBatchedArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((mfma_forward_batched<T, QN, WTX>), dim3(grid), dim3(256), 0, st, a);
+hipError_t batched_t(const MfmaBatchedArgs& a, int cus, hipStream_t st) {
+  auto kern = mfma_forward_batched<T, QN, WTX>;
+  // A persistent grid must be fully resident (a late block doubles the time),
+  // and a multiple of 8 so that the XCD-aware item order applies.
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
+  if (e != hipSuccess) return e;
+  const int total = a.first[a.count];
+  int grid = std::max(1, per_cu) * cus;
+  if (grid >= total) grid = total;
+  else grid = std::max(8, grid / 8 * 8);
+  hipLaunchKernelGGL(kern, dim3(std::max(1, grid)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t batched_any(const MfmaBatchedArgs& a, int qn, bool wtx, int grid, hipStream_t st) {
+hipError_t batched_any(const MfmaBatchedArgs& a, int qn, bool wtx, int cus, hipStream_t st) {
   constexpr int QMAX = kStack >= 8 ? 4 : kStack > 1 ? 8 : 16;
-  if (qn == 1) return wtx ? batched_t<T, 1, true>(a, grid, st) : batched_t<T, 1, false>(a, grid, st);
-  if (qn <= 4) return wtx ? batched_t<T, 4, true>(a, grid, st) : batched_t<T, 4, false>(a, grid, st);
-  return wtx ? batched_t<T, QMAX, true>(a, grid, st) : batched_t<T, QMAX, false>(a, grid, st);
+  if (qn == 1) return wtx ? batched_t<T, 1, true>(a, cus, st) : batched_t<T, 1, false>(a, cus, st);
+  if (qn <= 4) return wtx ? batched_t<T, 4, true>(a, cus, st) : batched_t<T, 4, false>(a, cus, st);
+  return wtx ? batched_t<T, QMAX, true>(a, cus, st) : batched_t<T, QMAX, false>(a, cus, st);
 }
 
 }  // namespace
@@ -740,9 +763,8 @@ hipError_t launch_mfma_batched(MfmaBatchedArgs& a, int storage, int cus, hipStre
     w.nbx = (w.ngroups + 3) / 4;
     a.first[i + 1] = a.first[i] + w.nbx * (mfma_batch_pad(w.B) / 16);
   }
-  const int grid = std::max(1, std::min(a.first[a.count], 4 * cus));
-  if (storage == DAS_STORE_F16) return batched_any<_Float16>(a, qn, wtx, grid, st);
-  return batched_any<uint16_t>(a, qn, wtx, grid, st);
+  if (storage == DAS_STORE_F16) return batched_any<_Float16>(a, qn, wtx, cus, st);
+  return batched_any<uint16_t>(a, qn, wtx, cus, st);
 }
 int mfma_chunks(int K) { return (K + CH - 1) / CH + 2; }
 

@@ -8,8 +8,8 @@ hipError_t tiled_forward_bf16(const Geom& g, const TileShape& ts, const Window& 
   return tiled::launch<uint16_t>(g, ts, w, ws, B, x, st);
 }
 size_t tiled_lds_bf16(const Geom& g, int bt, const Window& w) { return tiled::lds_bytes(g.Q, bt, w); }
-hipError_t tiled_batched_bf16(const BatchedArgs& a, int bt, int qn, bool wtx, int grid,
+hipError_t tiled_batched_bf16(const BatchedArgs& a, int bt, int qn, bool wtx, int cus,
                              hipStream_t st) {
-  return tiled::launch_batched<uint16_t>(a, bt, qn, wtx, grid, st);
+  return tiled::launch_batched<uint16_t>(a, bt, qn, wtx, cus, st);
 }
 }  // namespace dasmi

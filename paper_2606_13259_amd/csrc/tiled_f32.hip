@@ -8,8 +8,8 @@ hipError_t tiled_forward_f32(const Geom& g, const TileShape& ts, const Window& w
   return tiled::launch<float>(g, ts, w, ws, B, x, st);
 }
 size_t tiled_lds_f32(const Geom& g, int bt, const Window& w) { return tiled::lds_bytes(g.Q, bt, w); }
-hipError_t tiled_batched_f32(const BatchedArgs& a, int bt, int qn, bool wtx, int grid,
+hipError_t tiled_batched_f32(const BatchedArgs& a, int bt, int qn, bool wtx, int cus,
                              hipStream_t st) {
-  return tiled::launch_batched<float>(a, bt, qn, wtx, grid, st);
+  return tiled::launch_batched<float>(a, bt, qn, wtx, cus, st);
 }
 }  // namespace dasmi

@@ -382,10 +382,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void ti
                             smem, ktx_s);
 }
 
-// Several forward passes in one persistent launch: workgroup w processes work
-// items w, w + gridDim.x, ...; item i belongs to the plan p whose range
-// [first[p], first[p+1]) contains it and names one (tile, batch group) of that
-// plan (tiles deepest first, batch groups outermost).
+// Several forward passes in one persistent launch: in round r, workgroup w
+// processes work item r G + ((w + 104 r) mod G) (G = gridDim.x); item i
+// belongs to the plan p whose range [first[p], first[p+1]) contains it and
+// names one (tile, batch group) of that plan (tiles deepest first, batch
+// groups outermost).
 
 template <class T, int BT, int QN, bool WTX>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void tiled_forward_batched(
@@ -393,10 +394,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void ti
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int ktx_s[16];
   const int total = a.first[a.count];
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+  const unsigned G = gridDim.x;
+  for (int r = 0; r * (int)G < total; ++r) {
+    // The slot of this block rotates every round, so that it does not see the
+    // same lateral tile position (and amount of work) in every round.
+    const int item = r * (int)G + (int)((blockIdx.x + 104u * (unsigned)r) % G);
+    if (item >= total) continue;
     int p = 0;
     while (p + 1 < a.count && item >= a.first[p + 1]) ++p;
-    const PlanWork& w = a.p[p];
+    const PlanWork w = a.p[p];  // uniform index: copied once per item
     const int local = item - a.first[p];
     const int tile = local % w.ntiles, bg = local / w.ntiles;
     __syncthreads();  // the previous item no longer reads LDS
@@ -473,7 +479,7 @@ hipError_t launch(const Geom& g, const TileShape& ts, const Window& w, const voi
 }
 
 template <class T, int BT, int QN, bool WTX>
-hipError_t launch_batched_t(const BatchedArgs& a, int grid, hipStream_t st) {
+hipError_t launch_batched_t(const BatchedArgs& a, int cus, hipStream_t st) {
   const Window w0{0, 63};
   const size_t lds = lds_bytes_t<BT, QN>(w0);
   auto kern = tiled_forward_batched<T, BT, QN, WTX>;
@@ -482,30 +488,36 @@ hipError_t launch_batched_t(const BatchedArgs& a, int grid, hipStream_t st) {
         hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  // A persistent grid must be fully resident: a block that starts only after
+  // others have finished their whole share doubles the launch time.
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds);
+  if (e != hipSuccess) return e;
+  const int grid = std::max(1, std::min(a.first[a.count], std::max(1, per_cu) * cus));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, a);
   return hipGetLastError();
 }
 
 template <class T, int BT>
-hipError_t launch_batched_bt(const BatchedArgs& a, int qn, bool wtx, int grid, hipStream_t st) {
+hipError_t launch_batched_bt(const BatchedArgs& a, int qn, bool wtx, int cus, hipStream_t st) {
   switch (qn) {
-    case 1: return wtx ? launch_batched_t<T, BT, 1, true>(a, grid, st)
-                       : launch_batched_t<T, BT, 1, false>(a, grid, st);
-    case 4: return wtx ? launch_batched_t<T, BT, 4, true>(a, grid, st)
-                       : launch_batched_t<T, BT, 4, false>(a, grid, st);
-    case 8: return wtx ? launch_batched_t<T, BT, 8, true>(a, grid, st)
-                       : launch_batched_t<T, BT, 8, false>(a, grid, st);
-    default: return wtx ? launch_batched_t<T, BT, 16, true>(a, grid, st)
-                        : launch_batched_t<T, BT, 16, false>(a, grid, st);
+    case 1: return wtx ? launch_batched_t<T, BT, 1, true>(a, cus, st)
+                       : launch_batched_t<T, BT, 1, false>(a, cus, st);
+    case 4: return wtx ? launch_batched_t<T, BT, 4, true>(a, cus, st)
+                       : launch_batched_t<T, BT, 4, false>(a, cus, st);
+    case 8: return wtx ? launch_batched_t<T, BT, 8, true>(a, cus, st)
+                       : launch_batched_t<T, BT, 8, false>(a, cus, st);
+    default: return wtx ? launch_batched_t<T, BT, 16, true>(a, cus, st)
+                        : launch_batched_t<T, BT, 16, false>(a, cus, st);
   }
 }
 
 template <class T>
-hipError_t launch_batched(const BatchedArgs& a, int bt, int qn, bool wtx, int grid,
+hipError_t launch_batched(const BatchedArgs& a, int bt, int qn, bool wtx, int cus,
                           hipStream_t st) {
-  if (bt == 4) return launch_batched_bt<T, 4>(a, qn, wtx, grid, st);
-  if (bt == 2) return launch_batched_bt<T, 2>(a, qn, wtx, grid, st);
-  return launch_batched_bt<T, 1>(a, qn, wtx, grid, st);
+  if (bt == 4) return launch_batched_bt<T, 4>(a, qn, wtx, cus, st);
+  if (bt == 2) return launch_batched_bt<T, 2>(a, qn, wtx, cus, st);
+  return launch_batched_bt<T, 1>(a, qn, wtx, cus, st);
 }
 
 }  // namespace tiled
