@@ -160,11 +160,14 @@ das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int
 /* Several forward passes in one persistent launch (the batched form): for
  * i < count, plan plans[i] beamforms its prepared workspace ws[i] (batch[i]
  * items) into x[i] ([batch[i]][N_i] f32).  The launch walks one work list of
- * (plan, voxel tile, batch group) items with a fixed grid of workgroups, each
- * plan using its own tile shape.  Requirements: 1 <= count <= 16; all plans on
- * one device with the same storage type, each using the windowed algorithm
- * (DAS_ERR_UNSUPPORTED otherwise).  Results equal those of das_forward on each
- * plan. */
+ * (plan, voxel tile or column, batch group) items with a fixed grid of
+ * resident workgroups.  Requirements: 1 <= count <= 16; all plans on one
+ * device with the same storage type and the same algorithm for their batch,
+ * windowed (each plan with its own tile shape) or MFMA (DAS_ERR_UNSUPPORTED
+ * otherwise).  Results equal those of das_forward on each plan bit for bit.
+ * MFMA launches schedule their items through work counters owned by
+ * plans[0]: two batched launches led by the same plan must not run
+ * concurrently (on different streams). */
 das_status das_forward_batched(int32_t count, const das_plan* plans, const void* const* ws,
                                const int32_t* batch, float* const* x, void* stream);
 

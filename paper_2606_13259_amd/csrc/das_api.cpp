@@ -106,6 +106,7 @@ struct das_plan_s {
   double* d_txvec = nullptr;
   double* d_txoff = nullptr;
   int* d_txkind = nullptr;
+  unsigned* d_ctr = nullptr;  // work counters of persistent MFMA launches led by this plan
   const float* w_tx = nullptr;
   int algo = DAS_ALGO_AUTO;  // forced algorithm (AUTO = choose)
   int tile = 0;              // index into kTiles
@@ -332,6 +333,7 @@ das_status das_plan_create(das_plan* out, const das_config* cfg, int hip_device)
   if (e == hipSuccess) e = alloc_copy((void**)&p->d_txvec, txvec.data(), sizeof(double) * 3 * Q);
   if (e == hipSuccess) e = alloc_copy((void**)&p->d_txoff, txoff.data(), sizeof(double) * Q);
   if (e == hipSuccess) e = alloc_copy((void**)&p->d_txkind, txkind.data(), sizeof(int) * Q);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_ctr, mfma_batched_counter_bytes());
   if (e != hipSuccess) {
     das_plan_destroy(p);
     return e == hipErrorOutOfMemory ? fail(DAS_ERR_OOM, "hipMalloc failed") : hip_fail(e, "plan upload");
@@ -356,6 +358,7 @@ das_status das_plan_destroy(das_plan p) {
   if (p->d_txvec) (void)hipFree(p->d_txvec);
   if (p->d_txoff) (void)hipFree(p->d_txoff);
   if (p->d_txkind) (void)hipFree(p->d_txkind);
+  if (p->d_ctr) (void)hipFree(p->d_ctr);
   delete p;
   return DAS_OK;
 }
@@ -504,7 +507,8 @@ static das_status forward_batched_mfma(int32_t count, const das_plan* plans, con
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plans[0]->device);
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-  e = launch_mfma_batched(a, plans[0]->cfg.storage, cus, static_cast<hipStream_t>(stream));
+  e = launch_mfma_batched(a, plans[0]->d_ctr, plans[0]->cfg.storage, cus,
+                          static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "das_forward_batched launch");
   return DAS_OK;
 }

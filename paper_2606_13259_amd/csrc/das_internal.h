@@ -80,6 +80,7 @@ hipError_t launch_debug_delays(const Geom& g, const TileShape& ts, int q, int m0
 // Matrix-core locality form (f16 / bf16 storage): chunked batch-inner
 // workspace [Q][M][Kc][Bp][8].
 int mfma_tiles_per_wave(int B);  // 16-column MFMA tiles per wavefront (1, 2 or 4)
+int mfma_stack_tiles(int B);     // 16-column tiles per wavefront of the depth-stacked form (1, 2)
 int mfma_tile_width(int B);      // batch items per workspace tile (16 x tiles per wavefront)
 int mfma_batch_pad(int B);       // batch rounded up to the tile width
 int mfma_chunks(int K);
@@ -88,7 +89,8 @@ struct MfmaWork {
   Geom g;
   const void* ws;
   float* x;
-  int B, TW, Kc, ngx, ngy, ngroups, nbx;
+  int B, TW, Kc, ngx, ngy, ngroups, nbx;  // ngroups: wavefront columns
+  int nb;                                 // 16-column batch tiles per wavefront
 };
 struct MfmaBatchedArgs {
   MfmaWork p[MAX_BATCHED];
@@ -96,8 +98,12 @@ struct MfmaBatchedArgs {
   int count;
 };
 // Fills the derived fields (column counts, work-list ranges) of `a` from
-// g, ws, x, B, TW, Kc of each plan and launches the persistent MFMA kernel.
-hipError_t launch_mfma_batched(MfmaBatchedArgs& a, int storage, int cus, hipStream_t st);
+// g, ws, x, B, TW, Kc of each plan and launches the persistent MFMA kernel,
+// which schedules its items through the device counters `ctr`
+// (mfma_batched_counter_bytes(), zeroed on `st` before the launch).
+size_t mfma_batched_counter_bytes();
+hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, int cus,
+                               hipStream_t st);
 size_t mfma_workspace_elems(const Geom& g, int B);
 hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b0, int nb, int btot,
                                void* ws, hipStream_t st);

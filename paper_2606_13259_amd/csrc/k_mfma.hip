@@ -343,7 +343,7 @@ __device__ __forceinline__ void group_body(const Geom& g, const T* __restrict__ 
 // fragments of the groups that have taps in it (a wave-uniform test per
 // (group, chunk)), so a chunk read from L2 serves up to ZS groups.  Delays are
 // formed relative to the column centre.
-template <class T, int ZS, int QN, bool WTX>
+template <class T, int ZS, int NB, int QN, bool WTX>
 __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ ws, int B, int TW,
                                            int Kc, float* __restrict__ x, int ngx, int ngy,
                                            int col, int by) {
@@ -356,8 +356,8 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
   const int ix = gx * 4 + (vi & 3), iy = gy * 4 + (vi >> 2);
   const int M = g.M, K = g.K;
   const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
-  const int subs = TW / 16;
-  const int tile = by / subs, col0 = (by - tile * subs) * 16;
+  const int subs = TW / (16 * NB);
+  const int tile = by / subs, col0 = (by - tile * subs) * 16 * NB;
 
   double px, py, pz;
   tile_ref_point(g, gx * 4 + 1.5, gy * 4 + 1.5, gz0 + 0.5 * (ZS - 1), px, py, pz);
@@ -385,9 +385,11 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
   const T* wtile = ws + (size_t)tile * g.Q * q_el + (size_t)(col0 + vi) * CH;
   constexpr int BIG = 1 << 29;
 
-  f32x4 acc[ZS];
+  f32x4 acc[ZS][NB];
 #pragma unroll
-  for (int k = 0; k < ZS; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < ZS; ++k)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[k][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   for (int q0 = 0; q0 < g.Q; q0 += QN) {
     const int qn = min(QN, g.Q - q0);
@@ -499,12 +501,15 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
 #pragma unroll
           for (int k = 0; k < ZS; ++k) d[k] = t[k] > -BIG ? t[k] + CH - CH * c_lo : -BIG;
           for (int u0 = 0; u0 < nc; u0 += NCH) {
-            u32x4 Bf[NCH];
+            u32x4 Bf[NCH][NB];
 #pragma unroll
             for (int u = 0; u < NCH; ++u)
-              if (u0 + u < nc)
-                Bf[u] = *reinterpret_cast<const u32x4*>(
-                    cqq + (size_t)min(c_lo + u0 + u, Kc - 1) * chunk_el);
+              if (u0 + u < nc) {
+                const T* pc = cqq + (size_t)min(c_lo + u0 + u, Kc - 1) * chunk_el;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                  Bf[u][nb] = *reinterpret_cast<const u32x4*>(pc + nb * 16 * CH);
+              }
 #pragma unroll
             for (int k = 0; k < ZS; ++k) {
 #pragma unroll
@@ -513,8 +518,14 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
                 const int du = d[k] - CH * (u0 + u);
                 // does any lane hold a tap of group k in this chunk?
                 if (__ballot((unsigned)(du + 1) <= (unsigned)CH) == 0ull) continue;
-                acc[k] = Mma<T>::mma(place_pair(P[k], du), Bf[u], acc[k]);
-                if constexpr (Mma<T>::kSplit) acc[k] = Mma<T>::mma(place_pair(Plo[k], du), Bf[u], acc[k]);
+                const u32x4 A = place_pair(P[k], du);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[k][nb] = Mma<T>::mma(A, Bf[u][nb], acc[k][nb]);
+                if constexpr (Mma<T>::kSplit) {
+                  const u32x4 Al = place_pair(Plo[k], du);
+#pragma unroll
+                  for (int nb = 0; nb < NB; ++nb) acc[k][nb] = Mma<T>::mma(Al, Bf[u][nb], acc[k][nb]);
+                }
               }
             }
           }
@@ -523,16 +534,20 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
     }
   }
   const int jy = gy * 4 + row;
-  const int b = tile * TW + col0 + vi;
-  if (b >= B || jy >= g.n[1]) return;
+  if (jy >= g.n[1]) return;
 #pragma unroll
-  for (int k = 0; k < ZS; ++k) {
-    if (gz0 + k < 0) continue;
-    float* xb = x + (size_t)b * N + (size_t)g.n[0] * (jy + (size_t)g.n[1] * (gz0 + k));
+  for (int nb = 0; nb < NB; ++nb) {
+    const int b = tile * TW + col0 + nb * 16 + vi;
+    if (b >= B) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int jx = gx * 4 + r;
-      if (jx < g.n[0]) xb[jx] = acc[k][r];
+    for (int k = 0; k < ZS; ++k) {
+      if (gz0 + k < 0) continue;
+      float* xb = x + (size_t)b * N + (size_t)g.n[0] * (jy + (size_t)g.n[1] * (gz0 + k));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jx = gx * 4 + r;
+        if (jx < g.n[0]) xb[jx] = acc[k][nb][r];
+      }
     }
   }
 }
@@ -558,55 +573,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void m
   group_body<T, NB, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, grp, blockIdx.y);
 }
 
-template <class T, int ZS, int QN, bool WTX>
+template <class T, int ZS, int NB, int QN, bool WTX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward_stack(
     Geom g, const T* __restrict__ ws, int B, int TW, int Kc, float* __restrict__ x, int ngx,
     int ngy, int ncols) {
   const int col = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (col >= ncols) return;  // whole wavefront
-  stack_body<T, ZS, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y);
+  stack_body<T, ZS, NB, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y);
 }
 
 // Voxel groups per wavefront column of the depth-stacked form (1 = one group
 // per wavefront).
-constexpr int kStack = 2;
+constexpr int kStack = 4;
 
-// Persistent form: workgroups walk one list of (plan, block of 4 wavefront
-// columns, 16-item batch slice) items; plan i owns items first[i] ..
-// first[i+1]-1, block-major within its batch slices.  No LDS and no barriers,
-// so wavefronts with nothing to do simply skip an item.  Each item runs the
-// same body as a single-plan launch, so results are identical bit for bit.
+// Persistent form with dynamic scheduling.  Work items are (plan, wavefront
+// column, 16-item batch slice), plan i owning items first[i] .. first[i+1]-1
+// (columns fastest, deepest first).  The list is cut into runs of kRun
+// consecutive items dealt round-robin to the 8 XCDs (run j to XCD j mod 8);
+// each wavefront takes the next item of its XCD's runs from that XCD's
+// counter (one atomic per item), so neighbouring columns share an L2 and the
+// load balances dynamically, as hardware dispatch does for ordinary launches.
+// Each item runs the same body as a single-plan launch, so results are
+// identical bit for bit.  The counters are zeroed by zero_counters on the
+// same stream before every launch.
+constexpr unsigned kXcds = 8, kRun = 512;
+
+__global__ void zero_counters(unsigned* c) {
+  if (threadIdx.x < kXcds) c[threadIdx.x] = 0u;
+}
+
 template <class T, int QN, bool WTX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward_batched(
-    MfmaBatchedArgs a) {
-  const int total = a.first[a.count];
-  const unsigned G = gridDim.x;
-  for (int r = 0; r * (int)G < total; ++r) {
-    // Round r covers list positions r G .. r G + G - 1.  The slot of this
-    // block rotates by 104 per round: a static slot would give a block the
-    // same lateral position in every round (rounds span whole depth slices)
-    // and leave the launch waiting on the blocks of the array's centre.  The
-    // rotation is a multiple of 8 and G is a multiple of 8 (or covers the
-    // whole list), so v stays on this block's XCD and the remap hands each
-    // XCD runs of neighbouring items.
-    const int v = r * (int)G + (int)((blockIdx.x + 104u * (unsigned)r) % G);
-    if (v >= total) continue;
-    const int item = G % 8 == 0 ? xcd_remap(v, total) : v;
+    MfmaBatchedArgs a, unsigned* __restrict__ ctr) {
+  const long long total = a.first[a.count];
+  const unsigned xcd = blockIdx.x % kXcds;  // workgroups are dealt round-robin to the XCDs
+  for (;;) {
+    unsigned n = 0u;
+    if ((threadIdx.x & 63) == 0) n = atomicAdd(ctr + xcd, 1u);
+    n = __builtin_amdgcn_readfirstlane(n);
+    const long long v = ((long long)(n / kRun) * kXcds + xcd) * kRun + n % kRun;
+    if (v >= total) break;  // every later item of this XCD lies further on
+    const int item = (int)v;
     int i = 0;
     while (item >= a.first[i + 1]) ++i;
     // copy the plan's share out of the argument block (uniform index: scalar
     // loads once per item, not a memory access per use in the loops)
     const MfmaWork w = a.p[i];
     const int local = item - a.first[i];
-    const int bx = local % w.nbx, by = local / w.nbx;
-    const int col = bx * 4 + (threadIdx.x >> 6);
-    if (col >= w.ngroups) continue;
-    if constexpr (kStack > 1)
-      stack_body<T, kStack, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x, w.ngx,
-                                     w.ngy, col, by);
-    else
+    const int col = local % w.ngroups, by = local / w.ngroups;
+    // each plan runs with its own batch tiles per wavefront (w.nb, uniform),
+    // exactly as a single-plan launch would
+    if constexpr (kStack > 1) {
+      if (w.nb == 2)
+        stack_body<T, kStack, 2, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
+                                          w.ngx, w.ngy, col, by);
+      else
+        stack_body<T, kStack, 1, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
+                                          w.ngx, w.ngy, col, by);
+    } else {
       group_body<T, 1, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x, w.ngx,
                                 w.ngy, col, by);
+    }
   }
 }
 
@@ -682,33 +709,38 @@ hipError_t launch_nb(const Geom& g, const void* ws, int B, float* x, hipStream_t
   }
 }
 
-template <class T, int ZS, int QN, bool WTX>
+template <class T, int ZS, int NB, int QN, bool WTX>
 hipError_t launch_stack_t(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
   const int ngx = (g.n[0] + 3) / 4, ngy = (g.n[1] + 3) / 4;
   const int ncols = ngx * ngy * ((g.n[2] + ZS - 1) / ZS);
   const int TW = mfma_tile_width(B), Kc = mfma_chunks(g.K);
-  dim3 grid((ncols + 3) / 4, mfma_batch_pad(B) / 16);
-  hipLaunchKernelGGL((mfma_forward_stack<T, ZS, QN, WTX>), grid, dim3(256), 0, st, g,
+  dim3 grid((ncols + 3) / 4, mfma_batch_pad(B) / (16 * NB));
+  hipLaunchKernelGGL((mfma_forward_stack<T, ZS, NB, QN, WTX>), grid, dim3(256), 0, st, g,
                      static_cast<const T*>(ws), B, TW, Kc, x, ngx, ngy, ncols);
   return hipGetLastError();
 }
 
-template <class T, int ZS>
+template <class T, int ZS, int NB>
 hipError_t launch_stack(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
   constexpr int QMAX = ZS >= 8 ? 4 : 8;
   const bool wtx = g.w_tx != nullptr;
   const int qg = g.Q == 1 ? 1 : (g.Q <= 4 || QMAX == 4) ? 4 : 8;
   if (qg == 1)
-    return wtx ? launch_stack_t<T, ZS, 1, true>(g, ws, B, x, st) : launch_stack_t<T, ZS, 1, false>(g, ws, B, x, st);
+    return wtx ? launch_stack_t<T, ZS, NB, 1, true>(g, ws, B, x, st)
+               : launch_stack_t<T, ZS, NB, 1, false>(g, ws, B, x, st);
   if (qg == 4)
-    return wtx ? launch_stack_t<T, ZS, 4, true>(g, ws, B, x, st) : launch_stack_t<T, ZS, 4, false>(g, ws, B, x, st);
-  return wtx ? launch_stack_t<T, ZS, QMAX, true>(g, ws, B, x, st)
-             : launch_stack_t<T, ZS, QMAX, false>(g, ws, B, x, st);
+    return wtx ? launch_stack_t<T, ZS, NB, 4, true>(g, ws, B, x, st)
+               : launch_stack_t<T, ZS, NB, 4, false>(g, ws, B, x, st);
+  return wtx ? launch_stack_t<T, ZS, NB, QMAX, true>(g, ws, B, x, st)
+             : launch_stack_t<T, ZS, NB, QMAX, false>(g, ws, B, x, st);
 }
 
 template <class T>
 hipError_t launch_any(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
-  if constexpr (kStack > 1) return launch_stack<T, kStack>(g, ws, B, x, st);
+  if constexpr (kStack > 1) {
+    if (mfma_stack_tiles(B) == 2) return launch_stack<T, kStack, 2>(g, ws, B, x, st);
+    return launch_stack<T, kStack, 1>(g, ws, B, x, st);
+  }
   const int nb = mfma_tiles_per_wave(B);
   if (nb == 4) return launch_nb<T, 4>(g, ws, B, x, st);
   if (nb == 2) return launch_nb<T, 2>(g, ws, B, x, st);
@@ -716,39 +748,49 @@ hipError_t launch_any(const Geom& g, const void* ws, int B, float* x, hipStream_
 }
 
 template <class T, int QN, bool WTX>
-hipError_t batched_t(const MfmaBatchedArgs& a, int cus, hipStream_t st) {
+hipError_t batched_t(const MfmaBatchedArgs& a, unsigned* ctr, int cus, hipStream_t st) {
   auto kern = mfma_forward_batched<T, QN, WTX>;
-  // A persistent grid must be fully resident (a late block doubles the time),
-  // and a multiple of 8 so that the XCD-aware item order applies.
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
   if (e != hipSuccess) return e;
+  // resident workgroups only (a multiple of 8, so that each XCD holds the same
+  // number), never more wavefronts than items
   const int total = a.first[a.count];
   int grid = std::max(1, per_cu) * cus;
-  if (grid >= total) grid = total;
-  else grid = std::max(8, grid / 8 * 8);
-  hipLaunchKernelGGL(kern, dim3(std::max(1, grid)), dim3(256), 0, st, a);
+  grid = std::min(grid, std::max(8, (total + 3) / 4));
+  grid = std::max(8, grid / 8 * 8);
+  hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, st, ctr);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, a, ctr);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t batched_any(const MfmaBatchedArgs& a, int qn, bool wtx, int cus, hipStream_t st) {
+hipError_t batched_any(const MfmaBatchedArgs& a, unsigned* ctr, int qn, bool wtx, int cus,
+                       hipStream_t st) {
   constexpr int QMAX = kStack >= 8 ? 4 : kStack > 1 ? 8 : 16;
-  if (qn == 1) return wtx ? batched_t<T, 1, true>(a, cus, st) : batched_t<T, 1, false>(a, cus, st);
-  if (qn <= 4) return wtx ? batched_t<T, 4, true>(a, cus, st) : batched_t<T, 4, false>(a, cus, st);
-  return wtx ? batched_t<T, QMAX, true>(a, cus, st) : batched_t<T, QMAX, false>(a, cus, st);
+  if (qn == 1)
+    return wtx ? batched_t<T, 1, true>(a, ctr, cus, st) : batched_t<T, 1, false>(a, ctr, cus, st);
+  if (qn <= 4)
+    return wtx ? batched_t<T, 4, true>(a, ctr, cus, st) : batched_t<T, 4, false>(a, ctr, cus, st);
+  return wtx ? batched_t<T, QMAX, true>(a, ctr, cus, st) : batched_t<T, QMAX, false>(a, ctr, cus, st);
 }
 
 }  // namespace
 
 int mfma_tiles_per_wave(int B) { return B > 32 ? 4 : B > 16 ? 2 : 1; }
+int mfma_stack_tiles(int B) { return std::min(2, mfma_tiles_per_wave(B)); }
 int mfma_tile_width(int B) { return 16 * mfma_tiles_per_wave(B); }
 int mfma_batch_pad(int B) {
   const int tw = mfma_tile_width(B);
   return (B + tw - 1) / tw * tw;
 }
 
-hipError_t launch_mfma_batched(MfmaBatchedArgs& a, int storage, int cus, hipStream_t st) {
+size_t mfma_batched_counter_bytes() { return kXcds * sizeof(unsigned); }
+
+hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, int cus,
+                               hipStream_t st) {
   int qn = 1;
   bool wtx = false;
   a.first[0] = 0;
@@ -760,11 +802,12 @@ hipError_t launch_mfma_batched(MfmaBatchedArgs& a, int storage, int cus, hipStre
     w.ngx = (w.g.n[0] + 3) / 4;
     w.ngy = (w.g.n[1] + 3) / 4;
     w.ngroups = w.ngx * w.ngy * ((w.g.n[2] + kStack - 1) / kStack);  // wavefront columns
-    w.nbx = (w.ngroups + 3) / 4;
-    a.first[i + 1] = a.first[i] + w.nbx * (mfma_batch_pad(w.B) / 16);
+    w.nbx = 0;
+    w.nb = kStack > 1 ? mfma_stack_tiles(w.B) : 1;
+    a.first[i + 1] = a.first[i] + w.ngroups * (mfma_batch_pad(w.B) / (16 * w.nb));
   }
-  if (storage == DAS_STORE_F16) return batched_any<_Float16>(a, qn, wtx, cus, st);
-  return batched_any<uint16_t>(a, qn, wtx, cus, st);
+  if (storage == DAS_STORE_F16) return batched_any<_Float16>(a, ctr, qn, wtx, cus, st);
+  return batched_any<uint16_t>(a, ctr, qn, wtx, cus, st);
 }
 int mfma_chunks(int K) { return (K + CH - 1) / CH + 2; }
 
