@@ -373,13 +373,21 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
 }
 
 template <class T, int BT, int QN, bool WTX>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void tiled_forward(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void tiled_forward(
     Geom g, TileShape ts, Window win, const T* __restrict__ ws, int B, float* __restrict__ x,
     int ntx, int nty, int ntiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int ktx_s[16];
-  tile_body<T, BT, QN, WTX>(g, ts, win, ws, B, x, ntx, nty, ntiles, blockIdx.x, blockIdx.y * BT,
-                            smem, ktx_s);
+  // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs (each
+  // with its own L2); give every XCD runs of 16 consecutive tiles (neighbours
+  // that stage overlapping sample windows), runs interleaved across XCDs so
+  // that the depth-dependent work stays balanced.  The ragged last round
+  // keeps its order.
+  constexpr int X = 8, C = 16, per = X * C;
+  const int bx = (int)blockIdx.x;
+  const int tile = bx >= (int)gridDim.x / per * per ? bx : bx / per * per + (bx % per % X) * C + (bx % per) / X;
+  tile_body<T, BT, QN, WTX>(g, ts, win, ws, B, x, ntx, nty, ntiles, tile, blockIdx.y * BT, smem,
+                            ktx_s);
 }
 
 // Several forward passes in one persistent launch: in round r, workgroup w
