@@ -234,3 +234,39 @@ def test_persistent_batched_launch(gpu):
         xo = oracle.forward(y.numpy(), g)
         for b in range(B):
             check_close(x[b].cpu().numpy(), xo[b], REL_L2_F32, ABS_F32, f"batched {g.grid_dims} b={b}")
+
+
+@pytest.mark.parametrize("algo,storage,B", [("plain", "f32", 3), ("tiled", "f32", 3),
+                                             ("tiled", "f16", 5), ("mfma", "f16", 17)])
+def test_unusual_sizes(gpu, algo, storage, B):
+    """Element count not a multiple of the 64-lane culling blocks or the 512-entry
+    element passes (M = 1100), more transmits than one compile-time group
+    (Q = 20, three kinds), an odd K, an odd grid."""
+    das = _das()
+    rng = np.random.default_rng(77)
+    base = synth.cfg2(dims=(7, 5, 9), n_side=8)
+    pos = np.concatenate([synth.matrix_array(32, 0.3e-3), rng.uniform(-5e-3, 5e-3, (76, 3)) * [1, 1, 0]])
+    kinds = np.array([synth.TX_DIVERGING, synth.TX_PLANE, synth.TX_NONE, synth.TX_PLANE] * 5, np.int32)
+    vecs = []
+    for i, k in enumerate(kinds):
+        if k == synth.TX_DIVERGING:
+            vecs.append([rng.uniform(-3e-3, 3e-3), rng.uniform(-3e-3, 3e-3), -10e-3])
+        elif k == synth.TX_PLANE:
+            vecs.append(synth.plane_wave(rng.uniform(-8, 8), rng.uniform(-8, 8)))
+        else:
+            vecs.append([0.0, 0.0, 0.0])
+    g = base.replace(elem_pos=pos, elem_normal=None, tx_kind=kinds, tx_vec=np.array(vecs),
+                     tx_offset=rng.uniform(0, 5e-3, 20) * (kinds == synth.TX_DIVERGING),
+                     num_samples=1000, t0=2e-6)
+    y = synth.random_channel_data(g, B, seed=78)
+    say(f"unusual sizes M={g.M} Q={g.Q} K={g.K} grid={g.grid_dims} {algo} {storage} B={B}")
+    plan = das.Plan(g, max_batch=B, storage=storage, algo=algo)
+    x = plan.forward(y.to(gpu)).cpu().numpy()
+    items = [0, B - 1]
+    ynp = y.numpy()[items]
+    xo = oracle.forward(ynp, g)
+    for i, b in enumerate(items):
+        if storage == "f32":
+            check_close(x[b], xo[i], REL_L2_F32, ABS_F32, f"b={b}")
+        else:
+            check_close(x[b], xo[i], *lowp_bars(storage), f"b={b}")
