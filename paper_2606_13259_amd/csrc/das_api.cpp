@@ -472,8 +472,8 @@ das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, vo
   const Geom g = make_geom(p);
   const TileShape ts = tile_shape(p->tile);
   const Window w = make_window(p, ts);
-  const size_t lds = (size_t)16 * 8 * (w.pairs + 1) * 4 + 512 + (size_t)p->M * 2;
-  if (lds > kMaxLds) return fail(DAS_ERR_UNSUPPORTED, "adjoint windows do not fit in LDS");
+  if (adjoint_lds_bytes(g, w) > kMaxLds)
+    return fail(DAS_ERR_UNSUPPORTED, "adjoint windows do not fit in LDS");
   hipError_t e = launch_adjoint(g, ts, w, gx, batch, gy, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "das_adjoint launch");
   return DAS_OK;

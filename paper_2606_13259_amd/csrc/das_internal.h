@@ -71,6 +71,7 @@ hipError_t launch_reorder(const Geom& g, int storage, const float* y, int b0, in
 hipError_t launch_plain_forward(const Geom& g, const float* y, int B, float* x, hipStream_t st);
 hipError_t launch_tiled_forward(const Geom& g, int storage, const TileShape& ts, const Window& w,
                                 const void* ws, int B, float* x, hipStream_t st);
+size_t adjoint_lds_bytes(const Geom& g, const Window& w);
 hipError_t launch_adjoint(const Geom& g, const TileShape& ts, const Window& w, const float* gx,
                           int B, float* gy, hipStream_t st);
 hipError_t launch_grad_c(const Geom& g, const float* y, const float* gx, int B, float* dLdc,

@@ -11,6 +11,16 @@
 // (transmit, element) channels with LDS float atomics, then flushes every
 // nonzero window entry to global memory with one float atomic.  Neighbouring
 // voxels hit the same taps, so most of the scatter traffic stays in LDS.
+// The windows hold 32-bit fixed-point sums: LDS integer atomics run several
+// times faster than LDS float atomics on this chip.  Per (tile, transmit
+// group) the largest contribution magnitude cmax is reduced over the block
+// and the scale is the power of two S with cmax S < 2^22; each contribution
+// is rounded to the nearest integer (absolute error <= 2^-23 cmax), a sample
+// collects at most one term per voxel of the 256-voxel tile, so sums stay
+// below 2^30.  The flush converts back exactly (x 1/S).  Integer sums are
+// order-independent, so a tile's windows are deterministic.  The windows
+// are kept in ACOPIES private copies, chosen by the voxel's x index modulo
+// ACOPIES, to spread lanes that share a tap over different addresses.
 // The order of the float atomics is not fixed: results are reproducible to
 // FP32 rounding, not bit for bit.
 //
@@ -25,7 +35,11 @@ namespace {
 
 constexpr int QG = 16;
 constexpr int NT = 256;
-constexpr int MCA = 8;  // elements per adjoint chunk
+constexpr int MCA = 4;      // elements per adjoint chunk
+constexpr int ACOPIES = 2;  // private copies of the LDS windows (power of two)
+
+// Floats per window copy (a one-float pad puts the copies on different banks).
+__host__ __device__ inline int copy_stride(int P) { return QG * MCA * P + 1; }
 
 __global__ void fill_zero(float* __restrict__ p, size_t n) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -49,10 +63,11 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
                                                       int ntiles, int per_xcd) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int P = win.pairs + 1;  // window samples
-  float* accw = reinterpret_cast<float*>(smem);                       // [QG][MCA][P]
-  AInfo* minfo = reinterpret_cast<AInfo*>(accw + QG * MCA * P);        // [MCA]
+  const int cs = copy_stride(P);
+  int* accw = reinterpret_cast<int*>(smem);                           // [ACOPIES][QG][MCA][P] (+pad)
+  AInfo* minfo = reinterpret_cast<AInfo*>(accw + ACOPIES * cs);        // [MCA]
   int* ktxs = reinterpret_cast<int*>(minfo + MCA);                      // [QG]
-  int* wcount = ktxs + QG;                                              // [4]
+  int* wcount = ktxs + QG;                                              // [4] (also the scale reduction)
   uint16_t* act = reinterpret_cast<uint16_t*>(wcount + 4);              // [M]
 
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -81,6 +96,9 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
   const int nact = cull_elements(g, px, py, pz, hx, hy, hz, wcount, act);
   // a tile whose upstream gradient is zero everywhere scatters nothing
   if (__syncthreads_or(gv != 0.f) == 0) return;
+  // windows start at zero; every flush leaves the entries it reads at zero
+  for (int i = t; i < ACOPIES * cs; i += NT) accw[i] = 0;
+  int* const mycopy = accw + (lx & (ACOPIES - 1)) * cs;
 
   for (int q0 = 0; q0 < g.Q; q0 += QG) {
     const int qn = min(QG, g.Q - q0);
@@ -97,10 +115,22 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
         wq[q] = gv * ((g.w_tx && inside) ? g.w_tx[(size_t)(q0 + q) * N + n] : 1.f);
       }
     }
+    // fixed-point scale of this transmit group: max |contribution| over the
+    // tile (receive weights are <= 1), then S = 2^(22 - e) with cmax < 2^e
+    float cm = 0.f;
+#pragma unroll
+    for (int q = 0; q < QG; ++q) cm = fmaxf(cm, fabsf(wq[q]));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) cm = fmaxf(cm, __shfl_xor(cm, o));
+    if (lane == 0) wcount[wave] = __float_as_int(cm);  // non-negative: int order = float order
+    __syncthreads();
+    const float cmax = __int_as_float(max(max(wcount[0], wcount[1]), max(wcount[2], wcount[3])));
+    int e2 = 0;
+    (void)frexpf(cmax, &e2);                 // cmax < 2^e2
+    const float S = ldexpf(1.f, 22 - e2), invS = ldexpf(1.f, e2 - 22);
     for (int c0 = 0; c0 < nact; c0 += MCA) {
       const int mcn = min(MCA, nact - c0);
       __syncthreads();
-      for (int i = t; i < QG * MCA * P; i += NT) accw[i] = 0.f;
       if (t < mcn) {
         const int m = act[c0 + t];
         const RxRef r = make_rx_ref(g, m, px, py, pz);
@@ -112,7 +142,7 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
         const float w = rx_weight(g, mi.m, mi.ex + dx, mi.ey + dy, mi.ez + dz);
         if (__ballot(w != 0.f && gv != 0.f) == 0ull) continue;
         const float a = fmaf(delta_dist(mi.ex, mi.ey, mi.ez, mi.en, dx, dy, dz, dp2), fscf, mi.h);
-        float* base = accw + mc * P + win.dint;
+        int* base = mycopy + mc * P + win.dint;
 #pragma unroll
         for (int q = 0; q < QG; ++q) {
           if (q < qn) {
@@ -121,9 +151,10 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
             const float al = f - fl;
             const float c = w * wq[q];
             if (c != 0.f) {
-              float* p = base + q * MCA * P + (int)fl;
-              atomicAdd(p, c - c * al);
-              atomicAdd(p + 1, c * al);
+              int* p = base + q * MCA * P + (int)fl;
+              const float cs2 = c * S;  // exact: S is a power of two
+              atomicAdd(p, __float2int_rn(cs2 - cs2 * al));
+              atomicAdd(p + 1, __float2int_rn(cs2 * al));
             }
           }
         }
@@ -135,11 +166,16 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
         if (q >= qn || mc >= mcn) continue;
         const int j0 = ktxs[q] + minfo[mc].krx - win.dint;
         float* dst = gy + (((size_t)b * g.Q + q0 + q) * M + minfo[mc].m) * (size_t)K;
-        const float* src = accw + (q * MCA + mc) * P;
+        int* src = accw + (q * MCA + mc) * P;
         for (int p = lane; p < P; p += 64) {
-          const float v = src[p];
+          int iv = 0;
+#pragma unroll
+          for (int r = 0; r < ACOPIES; ++r) {
+            iv += src[r * cs + p];
+            src[r * cs + p] = 0;
+          }
           const int j = j0 + p;
-          if (v != 0.f && j >= 0 && j < K) atomicAdd(dst + j, v);
+          if (iv != 0 && j >= 0 && j < K) atomicAdd(dst + j, (float)iv * invS);
         }
       }
     }
@@ -253,6 +289,13 @@ __global__ void debug_delays(Geom g, TileShape ts, int q, int m0, int m1, int n0
 
 }  // namespace
 
+size_t adjoint_lds_bytes(const Geom& g, const Window& w) {
+  const int P = w.pairs + 1;
+  size_t lds = (size_t)ACOPIES * copy_stride(P) * 4 + MCA * sizeof(AInfo) + QG * 4 + 16 +
+               (size_t)g.M * 2;
+  return (lds + 15) & ~(size_t)15;
+}
+
 hipError_t launch_adjoint(const Geom& g, const TileShape& ts, const Window& w, const float* gx,
                           int B, float* gy, hipStream_t st) {
   hipError_t e = zero(gy, (size_t)B * g.Q * g.M * g.K, st);
@@ -261,9 +304,7 @@ hipError_t launch_adjoint(const Geom& g, const TileShape& ts, const Window& w, c
             ntz = (g.n[2] + ts.tz - 1) / ts.tz;
   const int ntiles = ntx * nty * ntz;
   const int per_xcd = (ntiles + 7) / 8;
-  const int P = w.pairs + 1;
-  size_t lds = (size_t)QG * MCA * P * 4 + MCA * sizeof(AInfo) + QG * 4 + 16 + (size_t)g.M * 2;
-  lds = (lds + 15) & ~(size_t)15;
+  const size_t lds = adjoint_lds_bytes(g, w);
   if (lds > 65536) {
     e = hipFuncSetAttribute((const void*)adjoint_scatter,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
