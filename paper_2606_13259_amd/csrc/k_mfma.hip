@@ -33,7 +33,7 @@
 // L1/L2 traffic (the bound of this form) by up to the stack depth.
 //
 // Delay formation is the tile-relative FP32 scheme of the VALU kernels with
-// the group (or column) centre as reference.  Weights are rounded to the operand type;
+// the column centre as reference.  Weights are rounded to the operand type;
 // for bf16 each weight is split into a high and a low bf16 part (two MFMAs
 // with the same samples) so that the weight rounding stays far below the
 // storage rounding.  Accumulation is FP32.
@@ -122,219 +122,6 @@ __device__ inline int row_max(int v) {
   v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, true));
   v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, true));
   return v;
-}
-
-// One wavefront: voxel group `grp` (deepest groups first: they see the most
-// receivers) for the 16 NB batch columns `by` of the workspace: tile
-// by / subs, columns col0 .. col0 + 16 NB - 1 of its TW (subs = TW / 16 NB).
-template <class T, int NB, int QN, bool WTX>
-__device__ __forceinline__ void group_body(const Geom& g, const T* __restrict__ ws, int B, int TW,
-                                           int Kc, float* __restrict__ x, int ngx, int ngy,
-                                           int grp, int by) {
-  const int lane = threadIdx.x & 63;
-  const int per_z = ngx * ngy;
-  const int gz = g.n[2] - 1 - grp / per_z;
-  const int gx = grp % ngx, gy = (grp / ngx) % ngy;
-  const int vi = lane & 15, row = lane >> 4;
-  const int ix = gx * 4 + (vi & 3), iy = gy * 4 + (vi >> 2);
-  const int M = g.M, K = g.K;
-  const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
-  const int subs = TW / (16 * NB);
-  const int tile = by / subs, col0 = (by - tile * subs) * 16 * NB;
-
-  double px, py, pz;
-  tile_ref_point(g, gx * 4 + 1.5, gy * 4 + 1.5, (double)gz, px, py, pz);
-  const float sx = (float)g.s[0], sy = (float)g.s[1];
-  const float dx = ((float)(vi & 3) - 1.5f) * sx, dy = ((float)(vi >> 2) - 1.5f) * sy, dz = 0.f;
-  const float dp2 = dx * dx + dy * dy;
-  const float fscf = (float)g.fsc;
-  const bool inside = in_grid(g, ix, iy, gz);
-  const int n = inside ? grid_index(g, ix, iy, gz) : 0;
-  const float Rg = 1.5f * sqrtf(sx * sx + sy * sy);
-  const bool hann = g.apod == DAS_APOD_HANN_FNUM;
-  const float cth = hann ? sqrtf(g.fourF2) * rsqrtf(1.f + g.fourF2) : -1.f;
-  const float sth = hann ? rsqrtf(1.f + g.fourF2) : 0.f;
-  // workspace strides in elements: chunk, (q, m) channel, transmit, tile
-  const uint32_t chunk_el = (uint32_t)TW * CH;
-  const size_t chan_el = (size_t)Kc * chunk_el;
-  const size_t q_el = (size_t)M * chan_el;
-  const T* wtile = ws + (size_t)tile * g.Q * q_el + (size_t)(col0 + vi) * CH;
-  constexpr int BIG = 1 << 29;
-
-  f32x4 acc[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  for (int q0 = 0; q0 < g.Q; q0 += QN) {
-    const int qn = min(QN, g.Q - q0);
-    TxRef mine = {};
-    if (lane < qn) mine = make_tx_ref(g, q0 + lane, px, py, pz);
-    float bq[QN], wq[WTX ? QN : 1];
-    int ktx[QN];
-#pragma unroll
-    for (int q = 0; q < QN; ++q) {
-      TxRef r;
-      r.kind = __shfl(mine.kind, q);
-      r.vx = __shfl(mine.vx, q);
-      r.vy = __shfl(mine.vy, q);
-      r.vz = __shfl(mine.vz, q);
-      r.vn = __shfl(mine.vn, q);
-      ktx[q] = __shfl(mine.ktx, q);
-      bq[q] = fmaf(delta_tx(r, dx, dy, dz, dp2), fscf, __shfl(mine.g, q));
-      if constexpr (WTX) wq[q] = (q < qn && inside) ? g.w_tx[(size_t)(q0 + q) * N + n] : 0.f;
-    }
-    for (int m0 = 0; m0 < M; m0 += 64) {
-      // one receiver per lane: group-level cone test and FP64 reference terms
-      const int me = m0 + lane;
-      bool on = me < M;
-      float rex = 0.f, rey = 0.f, rez = 0.f, ren = 0.f, rh = 0.f;
-      int rk = 0;
-      if (on) {
-        const double ex = px - g.elem[3 * me + 0];
-        const double ey = py - g.elem[3 * me + 1];
-        const double ez = pz - g.elem[3 * me + 2];
-        rex = (float)ex;
-        rey = (float)ey;
-        rez = (float)ez;
-        if (hann) {
-          float nx = 0.f, ny = 0.f, nz = 1.f;
-          if (g.enorm) {
-            nx = g.enorm[3 * me + 0];
-            ny = g.enorm[3 * me + 1];
-            nz = g.enorm[3 * me + 2];
-          }
-          on = sphere_in_cone(rex, rey, rez, nx, ny, nz, Rg, cth, sth);
-        }
-        if (on) {
-          const double R = sqrt(ex * ex + ey * ey + ez * ez);
-          const double fr = R * g.fsc;
-          const double fl = floor(fr);
-          ren = (float)R;
-          rh = (float)(fr - fl);
-          rk = (int)fl;
-        }
-      }
-      uint64_t mk = __ballot(on);
-      while (mk) {
-        // next (up to) four surviving receivers, one per row
-        int js[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          js[r] = mk ? __builtin_ctzll(mk) : -1;
-          mk &= mk - 1ull;
-        }
-        const int j = row == 0 ? js[0] : row == 1 ? js[1] : row == 2 ? js[2] : js[3];
-        const int src = j < 0 ? 0 : j;
-        const float ex = __shfl(rex, src), ey = __shfl(rey, src), ez = __shfl(rez, src);
-        const float en = __shfl(ren, src), h = __shfl(rh, src);
-        const int krx = __shfl(rk, src);
-        const int m = m0 + src;
-        const float w = j < 0 ? 0.f : rx_weight(g, m, ex + dx, ey + dy, ez + dz);
-        if (__ballot(w != 0.f) == 0ull) continue;
-        const float a = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, h);
-        const T* chan = wtile + (size_t)q0 * q_el + (size_t)m * chan_el;
-
-        // Per transmit: tap, packed weights and the chunk range of each
-        // receiver row (DPP min/max over its 16 voxels).  Transmits past qn
-        // (padding of the compile-time group) get zero weights and read the
-        // group's first channel.  Rows with no live tap start at chunk 0, so
-        // chunks c_lo and c_lo + 1 always exist (c_lo <= ceil(K/8) = Kc - 2).
-        struct Step {
-          uint32_t P, Plo;
-          int dv, c_lo, nrow;
-        };
-        auto step = [&](int q, float bqv, int ktxv, float wqv) {
-          Step r;
-          const bool live = q < qn;
-          const float f = a + bqv;
-          const int t = ktxv + krx + floor_i32(f);  // absolute tap index
-          const float al = frac_f32(f);
-          // taps outside [-1, K-1] read only zero padding
-          const bool valid = live && w != 0.f && t >= -1 && t <= K - 1;
-          const float wt = valid ? (WTX ? w * wqv : w) : 0.f;
-          const float w2 = wt * al, w1 = wt - w2;
-          r.P = Mma<T>::pack(w1, w2);
-          r.Plo = 0;
-          if constexpr (Mma<T>::kSplit) r.Plo = Mma<T>::pack(w1 - bf16_value(w1), w2 - bf16_value(w2));
-          const int tmin = row_min(valid ? t : BIG);
-          const int tmax = row_max(valid ? t : -BIG);
-          const bool any = tmax >= tmin;
-          r.c_lo = any ? (tmin + CH) >> 3 : 0;  // chunk holding sample tmin
-          r.nrow = any ? ((tmax + 1 + CH) >> 3) - r.c_lo + 1 : 0;
-          r.dv = valid ? t + CH - CH * r.c_lo : -BIG;  // slot of tap t in chunk c_lo
-          return r;
-        };
-        auto mma_chunk = [&](const Step& r, int u, const u32x4 (&Bf)[NB]) {
-          const u32x4 A = place_pair(r.P, r.dv - CH * u);
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[nb] = Mma<T>::mma(A, Bf[nb], acc[nb]);
-          if constexpr (Mma<T>::kSplit) {
-            const u32x4 Al = place_pair(r.Plo, r.dv - CH * u);
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[nb] = Mma<T>::mma(Al, Bf[nb], acc[nb]);
-          }
-        };
-        // Pass 1, branch-free: the first two chunks of every transmit (rows
-        // of compact groups span one or two chunks).
-        uint32_t rest = 0;  // transmits with a row that spans more than two chunks
-        const T* cq = chan;
-#pragma unroll
-        for (int q = 0; q < QN; ++q) {
-          const Step r = step(q, bq[q], ktx[q], WTX ? wq[WTX ? q : 0] : 1.f);
-          const T* p0 = cq + __mul24(r.c_lo, (int)chunk_el);
-          u32x4 B0[NB], B1[NB];
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            B0[nb] = *reinterpret_cast<const u32x4*>(p0 + nb * 16 * CH);
-            B1[nb] = *reinterpret_cast<const u32x4*>(p0 + chunk_el + nb * 16 * CH);
-          }
-          mma_chunk(r, 0, B0);
-          mma_chunk(r, 1, B1);
-          if (__ballot(r.nrow > 2)) rest |= 1u << q;
-          if (q + 1 < qn) cq += q_el;
-        }
-        // Pass 2 (wide tap spreads only): the remaining chunks, one transmit
-        // at a time, its reference terms taken again from the lane holding them.
-        while (rest) {
-          const int q = __builtin_ctz(rest);
-          rest &= rest - 1u;
-          TxRef tr;
-          tr.kind = __shfl(mine.kind, q);
-          tr.vx = __shfl(mine.vx, q);
-          tr.vy = __shfl(mine.vy, q);
-          tr.vz = __shfl(mine.vz, q);
-          tr.vn = __shfl(mine.vn, q);
-          const int ktxv = __shfl(mine.ktx, q);
-          const float bqv = fmaf(delta_tx(tr, dx, dy, dz, dp2), fscf, __shfl(mine.g, q));
-          const float wqv = WTX && inside ? g.w_tx[(size_t)(q0 + q) * N + n] : 1.f;
-          const Step r = step(q, bqv, ktxv, wqv);
-          const int nc = __builtin_amdgcn_readfirstlane(
-              max(max(__shfl(r.nrow, 0), __shfl(r.nrow, 16)), max(__shfl(r.nrow, 32), __shfl(r.nrow, 48))));
-          const T* cqq = chan + (size_t)q * q_el;
-          for (int u = 2; u < nc; ++u) {
-            const T* p = cqq + (size_t)min(r.c_lo + u, Kc - 1) * chunk_el;
-            u32x4 Bf[NB];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) Bf[nb] = *reinterpret_cast<const u32x4*>(p + nb * 16 * CH);
-            mma_chunk(r, u, Bf);
-          }
-        }
-      }
-    }
-  }
-  // result: lane holds batch column vi and voxel rows 4 row + r (x = r, y = row)
-  const int jy = gy * 4 + row;
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int b = tile * TW + col0 + nb * 16 + vi;
-    if (b >= B || jy >= g.n[1]) continue;
-    float* xb = x + (size_t)b * N + (size_t)g.n[0] * (jy + (size_t)g.n[1] * gz);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int jx = gx * 4 + r;
-      if (jx < g.n[0]) xb[jx] = acc[nb][r];
-    }
-  }
 }
 
 // Depth-stacked form: one wavefront owns ZS voxel groups stacked in depth
@@ -564,15 +351,6 @@ __device__ inline int xcd_remap(int b, int nblocks) {
   return r * per + (k % X) * C + k / X;
 }
 
-template <class T, int NB, int QN, bool WTX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward(
-    Geom g, const T* __restrict__ ws, int B, int TW, int Kc, float* __restrict__ x, int ngx,
-    int ngy, int ngroups) {
-  const int grp = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-  if (grp >= ngroups) return;  // whole wavefront
-  group_body<T, NB, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, grp, blockIdx.y);
-}
-
 template <class T, int ZS, int NB, int QN, bool WTX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward_stack(
     Geom g, const T* __restrict__ ws, int B, int TW, int Kc, float* __restrict__ x, int ngx,
@@ -582,8 +360,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void m
   stack_body<T, ZS, NB, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y);
 }
 
-// Voxel groups per wavefront column of the depth-stacked form (1 = one group
-// per wavefront).
+// Voxel groups per wavefront column of the depth-stacked form.
 constexpr int kStack = 4;
 
 // Persistent form with dynamic scheduling.  Work items are (plan, wavefront
@@ -623,17 +400,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void m
     const int col = local % w.ngroups, by = local / w.ngroups;
     // each plan runs with its own batch tiles per wavefront (w.nb, uniform),
     // exactly as a single-plan launch would
-    if constexpr (kStack > 1) {
-      if (w.nb == 2)
-        stack_body<T, kStack, 2, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
-                                          w.ngx, w.ngy, col, by);
-      else
-        stack_body<T, kStack, 1, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
-                                          w.ngx, w.ngy, col, by);
-    } else {
-      group_body<T, 1, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x, w.ngx,
-                                w.ngy, col, by);
-    }
+    if (w.nb == 2)
+      stack_body<T, kStack, 2, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
+                                        w.ngx, w.ngy, col, by);
+    else
+      stack_body<T, kStack, 1, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
+                                        w.ngx, w.ngy, col, by);
   }
 }
 
@@ -686,29 +458,6 @@ __global__ __launch_bounds__(256) void reorder_chunks(const float* __restrict__ 
   }
 }
 
-template <class T, int NB, int QN, bool WTX>
-hipError_t launch_t(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
-  const int ngx = (g.n[0] + 3) / 4, ngy = (g.n[1] + 3) / 4;
-  const int ngroups = ngx * ngy * g.n[2];
-  const int TW = mfma_tile_width(B), Kc = mfma_chunks(g.K);
-  dim3 grid((ngroups + 3) / 4, mfma_batch_pad(B) / TW);
-  hipLaunchKernelGGL((mfma_forward<T, NB, QN, WTX>), grid, dim3(256), 0, st, g,
-                     static_cast<const T*>(ws), B, TW, Kc, x, ngx, ngy, ngroups);
-  return hipGetLastError();
-}
-
-template <class T, int NB>
-hipError_t launch_nb(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
-  const bool wtx = g.w_tx != nullptr;
-  const int qg = g.Q == 1 ? 1 : g.Q <= 4 ? 4 : g.Q <= 8 ? 8 : 16;
-  switch (qg) {
-    case 1: return wtx ? launch_t<T, NB, 1, true>(g, ws, B, x, st) : launch_t<T, NB, 1, false>(g, ws, B, x, st);
-    case 4: return wtx ? launch_t<T, NB, 4, true>(g, ws, B, x, st) : launch_t<T, NB, 4, false>(g, ws, B, x, st);
-    case 8: return wtx ? launch_t<T, NB, 8, true>(g, ws, B, x, st) : launch_t<T, NB, 8, false>(g, ws, B, x, st);
-    default: return wtx ? launch_t<T, NB, 16, true>(g, ws, B, x, st) : launch_t<T, NB, 16, false>(g, ws, B, x, st);
-  }
-}
-
 template <class T, int ZS, int NB, int QN, bool WTX>
 hipError_t launch_stack_t(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
   const int ngx = (g.n[0] + 3) / 4, ngy = (g.n[1] + 3) / 4;
@@ -737,14 +486,8 @@ hipError_t launch_stack(const Geom& g, const void* ws, int B, float* x, hipStrea
 
 template <class T>
 hipError_t launch_any(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
-  if constexpr (kStack > 1) {
-    if (mfma_stack_tiles(B) == 2) return launch_stack<T, kStack, 2>(g, ws, B, x, st);
-    return launch_stack<T, kStack, 1>(g, ws, B, x, st);
-  }
-  const int nb = mfma_tiles_per_wave(B);
-  if (nb == 4) return launch_nb<T, 4>(g, ws, B, x, st);
-  if (nb == 2) return launch_nb<T, 2>(g, ws, B, x, st);
-  return launch_nb<T, 1>(g, ws, B, x, st);
+  if (mfma_stack_tiles(B) == 2) return launch_stack<T, kStack, 2>(g, ws, B, x, st);
+  return launch_stack<T, kStack, 1>(g, ws, B, x, st);
 }
 
 template <class T, int QN, bool WTX>
@@ -769,7 +512,7 @@ hipError_t batched_t(const MfmaBatchedArgs& a, unsigned* ctr, int cus, hipStream
 template <class T>
 hipError_t batched_any(const MfmaBatchedArgs& a, unsigned* ctr, int qn, bool wtx, int cus,
                        hipStream_t st) {
-  constexpr int QMAX = kStack >= 8 ? 4 : kStack > 1 ? 8 : 16;
+  constexpr int QMAX = kStack >= 8 ? 4 : 8;
   if (qn == 1)
     return wtx ? batched_t<T, 1, true>(a, ctr, cus, st) : batched_t<T, 1, false>(a, ctr, cus, st);
   if (qn <= 4)
@@ -803,7 +546,7 @@ hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, i
     w.ngy = (w.g.n[1] + 3) / 4;
     w.ngroups = w.ngx * w.ngy * ((w.g.n[2] + kStack - 1) / kStack);  // wavefront columns
     w.nbx = 0;
-    w.nb = kStack > 1 ? mfma_stack_tiles(w.B) : 1;
+    w.nb = mfma_stack_tiles(w.B);
     a.first[i + 1] = a.first[i] + w.ngroups * (mfma_batch_pad(w.B) / (16 * w.nb));
   }
   if (storage == DAS_STORE_F16) return batched_any<_Float16>(a, ctr, qn, wtx, cus, st);
