@@ -55,13 +55,29 @@ typedef enum {
 } das_status;
 
 typedef enum { DAS_TX_NONE = 0, DAS_TX_PLANE = 1, DAS_TX_DIVERGING = 2 } das_tx_kind;
-typedef enum { DAS_STORE_F32 = 0, DAS_STORE_F16 = 1, DAS_STORE_BF16 = 2 } das_storage;
+/* Workspace storage of the channel samples.  F16 and BF16 are the reduced
+ * precision of Sec. 3.3 (round to nearest even).  FP8_E4M3 is the lower
+ * precision the paper names as future work (Sec. 5): the OCP E4M3 8-bit format
+ * (4 exponent bits, bias 7, 3 fraction bits, largest finite 448), round to
+ * nearest even, with one power-of-two scale per batch item: an item whose
+ * largest magnitude is A = f 2^x (f in [0.5, 1)) is stored as y 2^(8-x), so
+ * that its samples span [-256, 256) and stay far from saturation; the forward
+ * removes the scale exactly.  An item with A = 0 or a non-finite sample is
+ * stored unscaled; NaN and +-inf samples are stored as NaN, finite magnitudes
+ * above 448 saturate.  FP8 runs in the windowed and MFMA algorithms (the plain
+ * one reads f32 and ignores the storage type, as for F16 and BF16). */
+typedef enum {
+  DAS_STORE_F32 = 0,
+  DAS_STORE_F16 = 1,
+  DAS_STORE_BF16 = 2,
+  DAS_STORE_FP8_E4M3 = 3
+} das_storage;
 typedef enum { DAS_APOD_UNIFORM = 0, DAS_APOD_HANN_FNUM = 1 } das_apod;
 typedef enum {
   DAS_ALGO_AUTO = 0,    /* tuned / heuristic choice among the three below */
   DAS_ALGO_PLAIN = 1,   /* one voxel per lane, direct gathers from y[B][Q][M][K] f32 */
   DAS_ALGO_TILED = 2,   /* voxel tiles, LDS sample windows, aperture culling */
-  DAS_ALGO_MFMA = 3     /* locality form on matrix cores (f16/bf16 storage only) */
+  DAS_ALGO_MFMA = 3     /* locality form on matrix cores (f16, bf16 or fp8 storage) */
 } das_algo;
 
 /* One transmit (observation) q: footnote to Eq. (1). */
@@ -112,7 +128,7 @@ das_status das_plan_set_sound_speed(das_plan p, double c);
 das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
 /* Force an algorithm (das_algo) for subsequent calls; AUTO restores the
  * plan's choice.  AUTO depends only on the storage type, the batch size and
- * what was fixed at plan creation: MFMA for f16/bf16 storage with batch >= 16,
+ * what was fixed at plan creation: MFMA for 16- or 8-bit storage with batch >= 16,
  * else windowed if any tile shape fits the geometry, else plain.  MFMA with
  * f32 storage returns DAS_ERR_UNSUPPORTED.  The algorithm decides the
  * workspace layout: a workspace must be prepared under the algorithm (and
@@ -132,12 +148,16 @@ das_status das_workspace_bytes(das_plan p, int32_t batch, size_t* bytes);
  *                 as ws to das_forward instead)
  *   TILED:        [Q][M][K][batch_total] in the plan's storage type, rounded
  *                 to nearest even;
- *   MFMA:         [Bp/TW][Q][M][Kc][TW][8] in f16/bf16 (rounded to nearest
- *                 even): 8-sample chunks, chunk kc holding samples
+ *   MFMA:         [Bp/TW][Q][M][Kc][TW][8] in f16/bf16/fp8 (rounded to
+ *                 nearest even): 8-sample chunks, chunk kc holding samples
  *                 8(kc-1) .. 8kc-1 (zero outside [0, K)), Kc = ceil(K/8) + 2;
  *                 batch tiles of TW = 16, 32 or 64 items for batch_total
  *                 <= 16, <= 32 or more, Bp = batch_total rounded up to TW
- *                 (Sec. 3.4 locality form). */
+ *                 (Sec. 3.4 locality form).
+ * FP8 workspaces end with a table of batch_total f32 values (the largest
+ * magnitude of each item, which fixes its scale) at the first 256-byte
+ * boundary after the samples; das_prepare first finds the largest magnitude of
+ * items b0 .. b0+nb-1 (one extra read of their y), then converts. */
 das_status das_prepare(das_plan p, const float* y, int32_t b0, int32_t nb, int32_t batch_total,
                        void* ws, void* stream);
 

@@ -84,6 +84,7 @@ int tiled_batch_per_thread(int storage, int B) {
 size_t tiled_lds_bytes(const Geom& g, int storage, int bt, const Window& w) {
   if (storage == DAS_STORE_F32) return tiled_lds_f32(g, bt, w);
   if (storage == DAS_STORE_F16) return tiled_lds_f16(g, bt, w);
+  if (storage == DAS_STORE_FP8_E4M3) return tiled_lds_fp8(g, bt, w);
   return tiled_lds_bf16(g, bt, w);
 }
 
@@ -91,6 +92,7 @@ hipError_t launch_tiled_forward(const Geom& g, int storage, const TileShape& ts,
                                 const void* ws, int B, float* x, hipStream_t st) {
   if (storage == DAS_STORE_F32) return tiled_forward_f32(g, ts, w, ws, B, x, st);
   if (storage == DAS_STORE_F16) return tiled_forward_f16(g, ts, w, ws, B, x, st);
+  if (storage == DAS_STORE_FP8_E4M3) return tiled_forward_fp8(g, ts, w, ws, B, x, st);
   return tiled_forward_bf16(g, ts, w, ws, B, x, st);
 }
 
@@ -178,7 +180,7 @@ hipError_t launch_windowed(const das_plan_s* p, const Geom& g, int tile, const v
 // The algorithm, and with it the workspace layout, depends only on the forced
 // algorithm and on what was decided at plan creation -- never on the current
 // tile or sound speed -- so das_prepare and das_forward always agree.
-// Batch size from which AUTO contracts on the matrix cores (16-bit storage).
+// Batch size from which AUTO contracts on the matrix cores (16- or 8-bit storage).
 constexpr int kMfmaMinBatch = 16;
 
 int choose_algo(const das_plan_s* p, int B) {
@@ -187,14 +189,37 @@ int choose_algo(const das_plan_s* p, int B) {
   return p->auto_tiled ? DAS_ALGO_TILED : DAS_ALGO_PLAIN;
 }
 
-size_t storage_bytes(int storage) { return storage == DAS_STORE_F32 ? 4 : 2; }
+size_t storage_bytes(int storage) {
+  return storage == DAS_STORE_F32 ? 4 : storage == DAS_STORE_FP8_E4M3 ? 1 : 2;
+}
 
-size_t ws_bytes(const das_plan_s* p, int B) {
+// Bytes of the samples of a workspace for B items.
+size_t ws_data_bytes(const das_plan_s* p, int B) {
   const int algo = choose_algo(p, B);
   const size_t elems = (size_t)B * p->Q * p->M * p->K;
   if (algo == DAS_ALGO_PLAIN) return elems * 4;
-  if (algo == DAS_ALGO_MFMA) return mfma_workspace_elems(make_geom(p), B) * 2;
+  if (algo == DAS_ALGO_MFMA) return mfma_workspace_elems(make_geom(p), B) * storage_bytes(p->cfg.storage);
   return elems * storage_bytes(p->cfg.storage);
+}
+
+// FP8 workspaces (windowed or MFMA layout) end with the per-item scale table:
+// B f32 values at the first 256-byte boundary after the samples.
+bool has_fp8_table(const das_plan_s* p, int B) {
+  return p->cfg.storage == DAS_STORE_FP8_E4M3 && choose_algo(p, B) != DAS_ALGO_PLAIN;
+}
+size_t fp8_table_offset(const das_plan_s* p, int B) { return (ws_data_bytes(p, B) + 255) & ~(size_t)255; }
+
+size_t ws_bytes(const das_plan_s* p, int B) {
+  if (has_fp8_table(p, B)) return fp8_table_offset(p, B) + sizeof(float) * (size_t)B;
+  return ws_data_bytes(p, B);
+}
+
+// The geometry of a call on workspace ws of B items (with the FP8 scale table).
+Geom call_geom(const das_plan_s* p, const void* ws, int B) {
+  Geom g = make_geom(p);
+  if (has_fp8_table(p, B))
+    g.amax = reinterpret_cast<const float*>(static_cast<const char*>(ws) + fp8_table_offset(p, B));
+  return g;
 }
 
 das_status check_plan(das_plan p) {
@@ -264,12 +289,12 @@ das_status das_plan_create(das_plan* out, const das_config* cfg, int hip_device)
     return fail(DAS_ERR_INVALID_ARG, "unknown apod");
   if (cfg->apod == DAS_APOD_HANN_FNUM && !(cfg->f_number > 0.0 && std::isfinite(cfg->f_number)))
     return fail(DAS_ERR_INVALID_ARG, "f_number must be finite and > 0");
-  if (cfg->storage < DAS_STORE_F32 || cfg->storage > DAS_STORE_BF16)
+  if (cfg->storage < DAS_STORE_F32 || cfg->storage > DAS_STORE_FP8_E4M3)
     return fail(DAS_ERR_INVALID_ARG, "unknown storage");
   if (cfg->algo < DAS_ALGO_AUTO || cfg->algo > DAS_ALGO_MFMA)
     return fail(DAS_ERR_INVALID_ARG, "unknown algo");
   if (cfg->algo == DAS_ALGO_MFMA && cfg->storage == DAS_STORE_F32)
-    return fail(DAS_ERR_UNSUPPORTED, "the MFMA form needs f16 or bf16 storage");
+    return fail(DAS_ERR_UNSUPPORTED, "the MFMA form needs f16, bf16 or fp8 storage");
   for (int m = 0; m < M; ++m)
     if (!finite3(cfg->element_pos + 3 * m)) return fail(DAS_ERR_INVALID_ARG, "element_pos not finite");
   std::vector<float> norm;
@@ -380,7 +405,7 @@ das_status das_plan_set_algo(das_plan p, int32_t algo) {
   if (das_status s = check_plan(p)) return s;
   if (algo < DAS_ALGO_AUTO || algo > DAS_ALGO_MFMA) return fail(DAS_ERR_INVALID_ARG, "unknown algo");
   if (algo == DAS_ALGO_MFMA && p->cfg.storage == DAS_STORE_F32)
-    return fail(DAS_ERR_UNSUPPORTED, "the MFMA form needs f16 or bf16 storage");
+    return fail(DAS_ERR_UNSUPPORTED, "the MFMA form needs f16, bf16 or fp8 storage");
   p->algo = algo;
   return DAS_OK;
 }
@@ -426,7 +451,7 @@ das_status das_prepare(das_plan p, const float* y, int32_t b0, int32_t nb, int32
     return fail(DAS_ERR_INVALID_ARG, "need 0 <= b0, 1 <= nb, b0 + nb <= batch_total");
   DeviceGuard dg(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const Geom g = make_geom(p);
+  const Geom g = call_geom(p, ws, batch_total);
   hipError_t e;
   const int algo = choose_algo(p, batch_total);
   if (algo == DAS_ALGO_PLAIN) {
@@ -448,7 +473,7 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
   if (das_status s = check_batch(p, batch)) return s;
   DeviceGuard dg(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const Geom g = make_geom(p);
+  const Geom g = call_geom(p, ws, batch);
   const int algo = choose_algo(p, batch);
   hipError_t e = hipSuccess;
   if (algo == DAS_ALGO_PLAIN) {
@@ -497,7 +522,7 @@ static das_status forward_batched_mfma(int32_t count, const das_plan* plans, con
   a.count = count;
   for (int i = 0; i < count; ++i) {
     MfmaWork& w = a.p[i];
-    w.g = make_geom(plans[i]);
+    w.g = call_geom(plans[i], ws[i], batch[i]);
     w.ws = ws[i];
     w.x = x[i];
     w.B = batch[i];
@@ -554,7 +579,7 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
   for (int i = 0; i < count; ++i) {
     const das_plan_s* p = plans[i];
     PlanWork& w = a.p[i];
-    w.g = make_geom(p);
+    w.g = call_geom(p, ws[i], batch[i]);
     w.ts = tile_shape(p->tile);
     w.win = make_window(p, w.ts);
     w.ws = ws[i];
@@ -572,6 +597,7 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (storage == DAS_STORE_F32) e = tiled_batched_f32(a, bt, qn, wtx, cus, st);
   else if (storage == DAS_STORE_F16) e = tiled_batched_f16(a, bt, qn, wtx, cus, st);
+  else if (storage == DAS_STORE_FP8_E4M3) e = tiled_batched_fp8(a, bt, qn, wtx, cus, st);
   else e = tiled_batched_bf16(a, bt, qn, wtx, cus, st);
   if (e != hipSuccess) return hip_fail(e, "das_forward_batched launch");
   return DAS_OK;
@@ -595,7 +621,7 @@ das_status das_autotune(das_plan p, int32_t batch, void* stream) {
   if (e == hipSuccess) e = hipEventCreate(&e1);
   int best = -1;
   float best_ms = 1e30f;
-  const Geom g = make_geom(p);
+  const Geom g = call_geom(p, ws, batch);  // zeroed workspace: FP8 items unscaled
   for (int ti = 0; ti < kNumTiles && e == hipSuccess; ++ti) {
     if (!tiled_fits(p, ti, batch)) continue;
     e = launch_windowed(p, g, ti, ws, batch, x, st);  // warm-up

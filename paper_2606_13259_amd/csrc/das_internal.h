@@ -27,6 +27,8 @@ struct Geom {
   double t0fs;           // t0 * fs  (samples)
   int apod;              // das_apod
   float fourF2;          // 4 F^2 (Hann f-number aperture test)
+  const float* amax;     // FP8 workspaces: [batch] largest magnitude per item (fixes
+                         // its scale), else nullptr
 };
 
 // Voxel tile handled by one workgroup of the windowed kernels.
@@ -62,12 +64,19 @@ hipError_t tiled_batched_f16(const BatchedArgs& a, int bt, int qn, bool wtx, int
                              hipStream_t st);
 hipError_t tiled_batched_bf16(const BatchedArgs& a, int bt, int qn, bool wtx, int cus,
                               hipStream_t st);
+hipError_t tiled_batched_fp8(const BatchedArgs& a, int bt, int qn, bool wtx, int cus,
+                             hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Host-side launchers (each returns the hipError_t of its launch).
 // ---------------------------------------------------------------------------
+// g.amax: the FP8 scale table of the workspace (FP8 storage only).
 hipError_t launch_reorder(const Geom& g, int storage, const float* y, int b0, int nb, int btot,
                           void* ws, hipStream_t st);
+// amax[b0 .. b0+nb-1] = largest |y| of each item of y[nb][Q][M][K] (the FP8
+// scale table; NaN compares above inf).
+hipError_t launch_item_absmax(const Geom& g, const float* y, int b0, int nb, float* amax,
+                              hipStream_t st);
 hipError_t launch_plain_forward(const Geom& g, const float* y, int B, float* x, hipStream_t st);
 hipError_t launch_tiled_forward(const Geom& g, int storage, const TileShape& ts, const Window& w,
                                 const void* ws, int B, float* x, hipStream_t st);
@@ -78,8 +87,8 @@ hipError_t launch_grad_c(const Geom& g, const float* y, const float* gx, int B, 
                          hipStream_t st);
 hipError_t launch_debug_delays(const Geom& g, const TileShape& ts, int q, int m0, int m1, int n0,
                                int n1, double* f_out, hipStream_t st);
-// Matrix-core locality form (f16 / bf16 storage): chunked batch-inner
-// workspace [Q][M][Kc][Bp][8].
+// Matrix-core locality form (f16 / bf16 / fp8 storage): chunked batch-inner
+// workspace [Bp/TW][Q][M][Kc][TW][8].
 int mfma_tiles_per_wave(int B);  // 16-column MFMA tiles per wavefront (1, 2 or 4)
 int mfma_stack_tiles(int B);     // 16-column tiles per wavefront of the depth-stacked form (1, 2)
 int mfma_tile_width(int B);      // batch items per workspace tile (16 x tiles per wavefront)
@@ -105,7 +114,7 @@ struct MfmaBatchedArgs {
 size_t mfma_batched_counter_bytes();
 hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, int cus,
                                hipStream_t st);
-size_t mfma_workspace_elems(const Geom& g, int B);
+size_t mfma_workspace_elems(const Geom& g, int B);  // samples (1, 2 bytes each)
 hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b0, int nb, int btot,
                                void* ws, hipStream_t st);
 hipError_t launch_mfma_forward(const Geom& g, int storage, const void* ws, int B, float* x,
@@ -118,9 +127,12 @@ hipError_t tiled_forward_f16(const Geom& g, const TileShape& ts, const Window& w
                              int B, float* x, hipStream_t st);
 hipError_t tiled_forward_bf16(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
                               int B, float* x, hipStream_t st);
+hipError_t tiled_forward_fp8(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
+                             int B, float* x, hipStream_t st);
 size_t tiled_lds_f32(const Geom& g, int bt, const Window& w);
 size_t tiled_lds_f16(const Geom& g, int bt, const Window& w);
 size_t tiled_lds_bf16(const Geom& g, int bt, const Window& w);
+size_t tiled_lds_fp8(const Geom& g, int bt, const Window& w);
 
 // LDS bytes the tiled forward kernel needs (0 if it cannot run this shape).
 size_t tiled_lds_bytes(const Geom& g, int storage, int bt, const Window& w);

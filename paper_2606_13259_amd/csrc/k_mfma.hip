@@ -19,13 +19,15 @@
 // are culled first (conservative sphere-cone test), and quads are formed from
 // the surviving receivers.
 //
-// Workspace ("batch-tiled chunks"): ws[Bp/TW][q][m][kc][TW][8] in f16 or bf16,
+// Workspace ("batch-tiled chunks"): ws[Bp/TW][q][m][kc][TW][8] in f16, bf16 or FP8,
 // chunk kc holding samples 8 (kc - 1) .. 8 kc - 1 (zero outside [0, K)),
 // Kc = ceil(K/8) + 2 chunks, TW = 16 NB batch items per tile (NB = 1, 2, 4 by
 // batch size) and Bp the batch rounded up to TW.  The B fragment of a lane
-// (batch item b, receiver row r) is one 16-byte load, the 16 lanes of a row
-// read 256 contiguous bytes, and the wavefronts of one batch tile sweep one
-// contiguous region.
+// (batch item b, receiver row r) is one 16-byte load (8 bytes for FP8), the
+// 16 lanes of a row read 256 (128) contiguous bytes, and the wavefronts of one
+// batch tile sweep one contiguous region.  FP8 (E4M3) codes are decoded to f16
+// operands in registers, exactly; the item's power-of-two scale is removed at
+// the output.
 //
 // A wavefront owns a column of kStack such groups stacked in depth: it loads
 // the union of their chunks once per receiver row and applies each loaded
@@ -38,6 +40,7 @@
 // with the same samples) so that the weight rounding stays far below the
 // storage rounding.  Accumulation is FP32.
 #include "das_device.h"
+#include "fp8.h"
 
 namespace dasmi {
 namespace {
@@ -46,6 +49,7 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf168 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int CH = 8;  // samples per chunk
 
@@ -80,6 +84,28 @@ template <> struct Mma<uint16_t> {  // bf16 bit patterns
   }
   __device__ static uint32_t pack(float a, float b) {
     return (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
+  }
+};
+
+// Workspace element type S -> MFMA operand type T and B-fragment load (8
+// samples of one batch item).  f16 and bf16 are stored as operands; FP8 E4M3
+// codes (8 bytes) are decoded to f16 in registers (exact), so the weights
+// stay f16 and only the bytes moved shrink.
+template <class S> struct Operand {
+  using T = S;
+  using Raw = u32x4;
+  __device__ static Raw load(const S* p) { return *reinterpret_cast<const u32x4*>(p); }
+  __device__ static u32x4 decode(Raw r) { return r; }
+};
+template <> struct Operand<uint8_t> {
+  using T = _Float16;
+  using Raw = u32x2;
+  __device__ static Raw load(const uint8_t* p) { return *reinterpret_cast<const u32x2*>(p); }
+  __device__ static u32x4 decode(Raw r) {
+    uint32_t a, b, c, d;
+    e4m3x4_to_f16x4(r.x, a, b);
+    e4m3x4_to_f16x4(r.y, c, d);
+    return u32x4{a, b, c, d};
   }
 };
 
@@ -130,10 +156,11 @@ __device__ inline int row_max(int v) {
 // fragments of the groups that have taps in it (a wave-uniform test per
 // (group, chunk)), so a chunk read from L2 serves up to ZS groups.  Delays are
 // formed relative to the column centre.
-template <class T, int ZS, int NB, int QN, bool WTX>
-__device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ ws, int B, int TW,
+template <class S, int ZS, int NB, int QN, bool WTX>
+__device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ ws, int B, int TW,
                                            int Kc, float* __restrict__ x, int ngx, int ngy,
                                            int col, int by) {
+  using T = typename Operand<S>::T;
   constexpr int NCH = ZS / 2 + 2;  // chunks loaded per step before the rare second pass
   const int lane = threadIdx.x & 63;
   const int per_z = ngx * ngy;
@@ -169,7 +196,7 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
   const uint32_t chunk_el = (uint32_t)TW * CH;
   const size_t chan_el = (size_t)Kc * chunk_el;
   const size_t q_el = (size_t)M * chan_el;
-  const T* wtile = ws + (size_t)tile * g.Q * q_el + (size_t)(col0 + vi) * CH;
+  const S* wtile = ws + (size_t)tile * g.Q * q_el + (size_t)(col0 + vi) * CH;
   constexpr int BIG = 1 << 29;
 
   f32x4 acc[ZS][NB];
@@ -254,7 +281,7 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
           anyw |= w[k] != 0.f;
         }
         if (__ballot(anyw) == 0ull) continue;
-        const T* cq = wtile + (size_t)q0 * q_el + (size_t)m * chan_el;
+        const S* cq = wtile + (size_t)q0 * q_el + (size_t)m * chan_el;
 #pragma unroll
         for (int q = 0; q < QN; ++q) {
           const bool live = q < qn;
@@ -282,20 +309,26 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
           const int nrow = any ? ((tmax + 1 + CH) >> 3) - c_lo + 1 : 0;
           const int nc = max(max(__builtin_amdgcn_readlane(nrow, 0), __builtin_amdgcn_readlane(nrow, 16)),
                              max(__builtin_amdgcn_readlane(nrow, 32), __builtin_amdgcn_readlane(nrow, 48)));
-          const T* cqq = cq + (size_t)(live ? q : 0) * q_el;
+          const S* cqq = cq + (size_t)(live ? q : 0) * q_el;
           // slot of each tap relative to this row's chunk c_lo
           int d[ZS];
 #pragma unroll
           for (int k = 0; k < ZS; ++k) d[k] = t[k] > -BIG ? t[k] + CH - CH * c_lo : -BIG;
           for (int u0 = 0; u0 < nc; u0 += NCH) {
+            typename Operand<S>::Raw Br[NCH][NB];
             u32x4 Bf[NCH][NB];
 #pragma unroll
             for (int u = 0; u < NCH; ++u)
               if (u0 + u < nc) {
-                const T* pc = cqq + (size_t)min(c_lo + u0 + u, Kc - 1) * chunk_el;
+                const S* pc = cqq + (size_t)min(c_lo + u0 + u, Kc - 1) * chunk_el;
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                  Bf[u][nb] = *reinterpret_cast<const u32x4*>(pc + nb * 16 * CH);
+                for (int nb = 0; nb < NB; ++nb) Br[u][nb] = Operand<S>::load(pc + nb * 16 * CH);
+              }
+#pragma unroll
+            for (int u = 0; u < NCH; ++u)
+              if (u0 + u < nc) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) Bf[u][nb] = Operand<S>::decode(Br[u][nb]);
               }
 #pragma unroll
             for (int k = 0; k < ZS; ++k) {
@@ -326,6 +359,8 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
   for (int nb = 0; nb < NB; ++nb) {
     const int b = tile * TW + col0 + nb * 16 + vi;
     if (b >= B) continue;
+    int e = 0;  // FP8: the item was stored as y 2^e
+    if constexpr (__is_same(S, uint8_t)) e = fp8_item_exponent(g.amax[b]);
 #pragma unroll
     for (int k = 0; k < ZS; ++k) {
       if (gz0 + k < 0) continue;
@@ -333,7 +368,12 @@ __device__ __forceinline__ void stack_body(const Geom& g, const T* __restrict__ 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int jx = gx * 4 + r;
-        if (jx < g.n[0]) xb[jx] = acc[k][nb][r];
+        if (jx < g.n[0]) {
+          if constexpr (__is_same(S, uint8_t))
+            xb[jx] = ldexpf(acc[k][nb][r], -e);
+          else
+            xb[jx] = acc[k][nb][r];
+        }
       }
     }
   }
@@ -418,7 +458,8 @@ constexpr int RC = 32;  // chunks per reorder tile
 template <class T>
 __global__ __launch_bounds__(256) void reorder_chunks(const float* __restrict__ y, int Q, int M,
                                                       int K, int Kc, int nb, int b0, int TW,
-                                                      T* __restrict__ ws) {
+                                                      T* __restrict__ ws,
+                                                      const float* __restrict__ amax) {
   __shared__ float tile[16][RC * CH + 1];
   const long long QM = (long long)Q * M;
   const int t = threadIdx.x;
@@ -438,20 +479,28 @@ __global__ __launch_bounds__(256) void reorder_chunks(const float* __restrict__ 
       const int kcl = o >> 4, i = o & 15;
       const int kc = kc0 + kcl, b = i0 + i;
       if (kc < Kc && b < nb) {
+        const int ba = b0 + b, bt = ba / TW;
+        T* dst = ws + (((long long)bt * QM + qm) * Kc + kc) * TW * CH + (long long)(ba - bt * TW) * CH;
         uint32_t v[CH];
+        if constexpr (__is_same(T, uint8_t)) {
+          // FP8: the item is stored as y 2^e
+          const int e = fp8_item_exponent(amax[ba]);
 #pragma unroll
-        for (int s = 0; s < CH; ++s) {
-          const float f = tile[i][kcl * CH + s];
-          if constexpr (__is_same(T, _Float16))
-            v[s] = f16_bits(f);
-          else
-            v[s] = bf16_bits(f);
+          for (int s = 0; s < CH; ++s) v[s] = e4m3_bits(ldexpf(tile[i][kcl * CH + s], e));
+          *reinterpret_cast<u32x2*>(dst) = u32x2{v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24),
+                                                 v[4] | (v[5] << 8) | (v[6] << 16) | (v[7] << 24)};
+        } else {
+#pragma unroll
+          for (int s = 0; s < CH; ++s) {
+            const float f = tile[i][kcl * CH + s];
+            if constexpr (__is_same(T, _Float16))
+              v[s] = f16_bits(f);
+            else
+              v[s] = bf16_bits(f);
+          }
+          *reinterpret_cast<u32x4*>(dst) = u32x4{v[0] | (v[1] << 16), v[2] | (v[3] << 16),
+                                                 v[4] | (v[5] << 16), v[6] | (v[7] << 16)};
         }
-        const u32x4 o4{v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
-                       v[6] | (v[7] << 16)};
-        const int ba = b0 + b, tile = ba / TW;
-        *reinterpret_cast<u32x4*>(ws + (((long long)tile * QM + qm) * Kc + kc) * TW * CH +
-                                  (long long)(ba - tile * TW) * CH) = o4;
       }
     }
     __syncthreads();
@@ -550,6 +599,7 @@ hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, i
     a.first[i + 1] = a.first[i] + w.ngroups * (mfma_batch_pad(w.B) / (16 * w.nb));
   }
   if (storage == DAS_STORE_F16) return batched_any<_Float16>(a, ctr, qn, wtx, cus, st);
+  if (storage == DAS_STORE_FP8_E4M3) return batched_any<uint8_t>(a, ctr, qn, wtx, cus, st);
   return batched_any<uint16_t>(a, ctr, qn, wtx, cus, st);
 }
 int mfma_chunks(int K) { return (K + CH - 1) / CH + 2; }
@@ -563,18 +613,25 @@ hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b
   const int Kc = mfma_chunks(g.K), TW = mfma_tile_width(btot);
   const long long QM = (long long)g.Q * g.M;
   const dim3 grid((Kc + RC - 1) / RC, (unsigned)std::min<long long>(QM, 65535), (nb + 15) / 16);
-  if (storage == DAS_STORE_F16)
+  if (storage == DAS_STORE_F16) {
     hipLaunchKernelGGL(reorder_chunks<_Float16>, grid, dim3(256), 0, st, y, g.Q, g.M, g.K, Kc, nb,
-                       b0, TW, static_cast<_Float16*>(ws));
-  else
+                       b0, TW, static_cast<_Float16*>(ws), nullptr);
+  } else if (storage == DAS_STORE_FP8_E4M3) {
+    hipError_t e = launch_item_absmax(g, y, b0, nb, const_cast<float*>(g.amax), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reorder_chunks<uint8_t>, grid, dim3(256), 0, st, y, g.Q, g.M, g.K, Kc, nb,
+                       b0, TW, static_cast<uint8_t*>(ws), g.amax);
+  } else {
     hipLaunchKernelGGL(reorder_chunks<uint16_t>, grid, dim3(256), 0, st, y, g.Q, g.M, g.K, Kc, nb,
-                       b0, TW, static_cast<uint16_t*>(ws));
+                       b0, TW, static_cast<uint16_t*>(ws), nullptr);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_mfma_forward(const Geom& g, int storage, const void* ws, int B, float* x,
                                hipStream_t st) {
   if (storage == DAS_STORE_F16) return launch_any<_Float16>(g, ws, B, x, st);
+  if (storage == DAS_STORE_FP8_E4M3) return launch_any<uint8_t>(g, ws, B, x, st);
   return launch_any<uint16_t>(g, ws, B, x, st);
 }
 

@@ -39,6 +39,7 @@
 // unrolls); a group that is not full is padded with zero-filled windows.
 #pragma once
 #include "das_device.h"
+#include "fp8.h"
 
 namespace dasmi {
 namespace tiled {
@@ -57,6 +58,9 @@ template <> __device__ inline float to_f32<float>(float v) { return v; }
 template <> __device__ inline float to_f32<_Float16>(_Float16 v) { return (float)v; }
 template <> __device__ inline float to_f32<uint16_t>(uint16_t v) {
   return __uint_as_float(((uint32_t)v) << 16);
+}
+template <> __device__ inline float to_f32<uint8_t>(uint8_t v) {  // FP8 E4M3 code
+  return e4m3_to_f32(v);
 }
 
 // Elements per chunk: QN * MC * BT = 64 windows of at most 64 samples
@@ -368,7 +372,12 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
   if (inside) {
 #pragma unroll
     for (int b = 0; b < BT; ++b)
-      if (b0 + b < B) x[(size_t)(b0 + b) * N + n] = acc[b];
+      if (b0 + b < B) {
+        if constexpr (__is_same(T, uint8_t))  // FP8: the item was stored as y 2^e
+          x[(size_t)(b0 + b) * N + n] = ldexpf(acc[b], -fp8_item_exponent(g.amax[b0 + b]));
+        else
+          x[(size_t)(b0 + b) * N + n] = acc[b];
+      }
   }
 }
 

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libdas_mi355x.so")
 
 DAS_OK, DAS_ERR_INVALID_ARG, DAS_ERR_UNSUPPORTED, DAS_ERR_HIP, DAS_ERR_OOM = 0, -1, -2, -3, -4
 TX_NONE, TX_PLANE, TX_DIVERGING = 0, 1, 2
-STORE = {"f32": 0, "f16": 1, "bf16": 2}
+STORE = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
 APOD_UNIFORM, APOD_HANN = 0, 1
 ALGO = {"auto": 0, "plain": 1, "tiled": 2, "mfma": 3}
 ALGO_NAME = {v: k for k, v in ALGO.items()}

@@ -40,7 +40,7 @@ def _cfg(**over):
 @pytest.mark.parametrize("field,value", [
     ("num_samples", 1), ("num_elements", 0), ("num_tx", 0), ("max_batch", 0),
     ("sound_speed", 0.0), ("sound_speed", float("nan")), ("fs", -1.0), ("apod", 7),
-    ("storage", 3), ("algo", 9),
+    ("storage", 4), ("storage", -1), ("algo", 9),
 ])
 def test_plan_create_rejects_bad_config(field, value):
     das, L, cfg, keep = _cfg(**{field: value})

@@ -61,7 +61,7 @@ def cfg2_blocks():
 
 
 @pytest.mark.parametrize("storage,algo", [("f32", "plain"), ("f32", "tiled"), ("f16", "tiled"),
-                                          ("bf16", "tiled")])
+                                          ("bf16", "tiled"), ("fp8", "tiled")])
 def test_cfg2_subblocks(gpu, cfg2_blocks, storage, algo):
     das = _das()
     g, y, blocks = cfg2_blocks
@@ -73,7 +73,7 @@ def test_cfg2_subblocks(gpu, cfg2_blocks, storage, algo):
         else:
             check_close(x, xo, *lowp_bars(storage), f"cfg2 block {sub.grid_dims} {storage} {algo}")
             # kernel error alone: oracle on the values the workspace holds
-            xr = oracle.forward(round_like_storage(y.cpu().numpy(), storage)[None], sub)[0]
+            xr = oracle.forward(round_like_storage(y.cpu().numpy()[None], storage), sub)[0]
             check_close(x, xr, REL_L2_F32, ABS_F32, f"  vs oracle on {storage}-rounded data")
 
 
@@ -237,7 +237,8 @@ def test_persistent_batched_launch(gpu):
 
 
 @pytest.mark.parametrize("algo,storage,B", [("plain", "f32", 3), ("tiled", "f32", 3),
-                                             ("tiled", "f16", 5), ("mfma", "f16", 17)])
+                                             ("tiled", "f16", 5), ("mfma", "f16", 17),
+                                             ("tiled", "fp8", 3), ("mfma", "fp8", 17)])
 def test_unusual_sizes(gpu, algo, storage, B):
     """Element count not a multiple of the 64-lane culling blocks or the 512-entry
     element passes (M = 1100), more transmits than one compile-time group
