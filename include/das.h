@@ -35,6 +35,9 @@
  *   - Non-finite inputs propagate unchecked.
  *   - A plan is not safe to mutate from several threads; enqueuing work from
  *     one thread per stream on a plan that is not being mutated is safe.
+ *     MFMA forwards led by one plan (das_forward and das_forward_batched)
+ *     take the plan's 64 sets of work counters in turn: at most 64 of them
+ *     may execute at the same time on different streams.
  */
 #ifndef DAS_MI355X_H
 #define DAS_MI355X_H
@@ -185,9 +188,12 @@ das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int
  * device with the same storage type and the same algorithm for their batch,
  * windowed (each plan with its own tile shape) or MFMA (DAS_ERR_UNSUPPORTED
  * otherwise).  Results equal those of das_forward on each plan bit for bit.
- * MFMA launches schedule their items through work counters owned by
- * plans[0]: two batched launches led by the same plan must not run
- * concurrently (on different streams). */
+ * MFMA launches schedule their items dynamically through one of the 64
+ * sets of work counters owned by plans[0] (the sets are taken in turn, so at
+ * most 64 MFMA launches led by one plan may execute at the same time on
+ * different streams).  A single-plan das_forward with the MFMA algorithm runs
+ * through this persistent kernel too when that gives the plan the same batch
+ * tiles per wavefront as the plain launch. */
 das_status das_forward_batched(int32_t count, const das_plan* plans, const void* const* ws,
                                const int32_t* batch, float* const* x, void* stream);
 

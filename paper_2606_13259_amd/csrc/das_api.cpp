@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -33,6 +34,9 @@ das_status hip_fail(hipError_t e, const char* what) {
 const int kTiles[][3] = {{8, 8, 4}, {16, 4, 4}, {4, 8, 8}, {16, 8, 2},
                          {8, 4, 8}, {16, 16, 1}, {32, 8, 1}, {4, 4, 16}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+// Counter sets per plan for persistent MFMA launches (launches of one plan
+// that overlap on different streams: at most this many).
+constexpr unsigned kCounterSets = 64;
 
 int ilog2(int v) {
   int l = 0;
@@ -108,7 +112,11 @@ struct das_plan_s {
   double* d_txvec = nullptr;
   double* d_txoff = nullptr;
   int* d_txkind = nullptr;
-  unsigned* d_ctr = nullptr;  // work counters of persistent MFMA launches led by this plan
+  // Work counters of persistent MFMA launches led by this plan: kCounterSets
+  // sets used in turn, so that launches that overlap on different streams use
+  // different sets.
+  unsigned* d_ctr = nullptr;
+  std::atomic<unsigned> ctr_next{0};
   const float* w_tx = nullptr;
   int algo = DAS_ALGO_AUTO;  // forced algorithm (AUTO = choose)
   int tile = 0;              // index into kTiles
@@ -358,7 +366,7 @@ das_status das_plan_create(das_plan* out, const das_config* cfg, int hip_device)
   if (e == hipSuccess) e = alloc_copy((void**)&p->d_txvec, txvec.data(), sizeof(double) * 3 * Q);
   if (e == hipSuccess) e = alloc_copy((void**)&p->d_txoff, txoff.data(), sizeof(double) * Q);
   if (e == hipSuccess) e = alloc_copy((void**)&p->d_txkind, txkind.data(), sizeof(int) * Q);
-  if (e == hipSuccess) e = hipMalloc((void**)&p->d_ctr, mfma_batched_counter_bytes());
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_ctr, kCounterSets * mfma_batched_counter_bytes());
   if (e != hipSuccess) {
     das_plan_destroy(p);
     return e == hipErrorOutOfMemory ? fail(DAS_ERR_OOM, "hipMalloc failed") : hip_fail(e, "plan upload");
@@ -467,6 +475,9 @@ das_status das_prepare(das_plan p, const float* y, int32_t b0, int32_t nb, int32
   return DAS_OK;
 }
 
+static das_status forward_batched_mfma(int32_t count, const das_plan* plans, const void* const* ws,
+                                       const int32_t* batch, float* const* x, void* stream);
+
 das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void* stream) {
   if (das_status s = check_plan(p)) return s;
   if (!ws || !x) return fail(DAS_ERR_INVALID_ARG, "ws or x is NULL");
@@ -482,6 +493,9 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
     if (!tiled_fits(p, p->tile, batch))
       return fail(DAS_ERR_UNSUPPORTED, "tile windows do not fit in LDS for this geometry");
     e = launch_windowed(p, g, p->tile, ws, batch, x, st);
+  } else if (mfma_prefers_persistent(p->cfg.storage, batch)) {
+    // the persistent kernel with one plan: same results, dynamic balance
+    return forward_batched_mfma(1, &p, &ws, &batch, &x, stream);
   } else {
     e = launch_mfma_forward(g, p->cfg.storage, ws, batch, x, st);
   }
@@ -532,7 +546,10 @@ static das_status forward_batched_mfma(int32_t count, const das_plan* plans, con
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plans[0]->device);
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-  e = launch_mfma_batched(a, plans[0]->d_ctr, plans[0]->cfg.storage, cus,
+  das_plan_s* lead = plans[0];
+  unsigned* ctr = lead->d_ctr + (size_t)(lead->ctr_next.fetch_add(1u) % kCounterSets) *
+                                    (mfma_batched_counter_bytes() / sizeof(unsigned));
+  e = launch_mfma_batched(a, ctr, lead->cfg.storage, cus,
                           static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "das_forward_batched launch");
   return DAS_OK;

@@ -90,7 +90,7 @@ hipError_t launch_debug_delays(const Geom& g, const TileShape& ts, int q, int m0
 // Matrix-core locality form (f16 / bf16 / fp8 storage): chunked batch-inner
 // workspace [Bp/TW][Q][M][Kc][TW][8].
 int mfma_tiles_per_wave(int B);  // 16-column MFMA tiles per wavefront (1, 2 or 4)
-int mfma_stack_tiles(int B);     // 16-column tiles per wavefront of the depth-stacked form (1, 2)
+int mfma_stack_tiles(int B);     // 16-column tiles per wavefront of the depth-stacked form (1, 2, 4)
 int mfma_tile_width(int B);      // batch items per workspace tile (16 x tiles per wavefront)
 int mfma_batch_pad(int B);       // batch rounded up to the tile width
 int mfma_chunks(int K);
@@ -112,6 +112,8 @@ struct MfmaBatchedArgs {
 // which schedules its items through the device counters `ctr`
 // (mfma_batched_counter_bytes(), zeroed on `st` before the launch).
 size_t mfma_batched_counter_bytes();
+// Whether a single-plan forward should use the persistent kernel.
+bool mfma_prefers_persistent(int storage, int B);
 hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, int cus,
                                hipStream_t st);
 size_t mfma_workspace_elems(const Geom& g, int B);  // samples (1, 2 bytes each)

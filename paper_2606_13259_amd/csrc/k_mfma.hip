@@ -151,15 +151,18 @@ __device__ inline int row_max(int v) {
 }
 
 // Depth-stacked form: one wavefront owns ZS voxel groups stacked in depth
-// (a 4 x 4 x ZS column) for 16 batch columns.  Per receiver row it loads the
+// (a 4 x 4 x ZS column) for 16 NB batch columns.  Per receiver row it loads the
 // union of the groups' chunks once, and applies to each loaded chunk the A
 // fragments of the groups that have taps in it (a wave-uniform test per
 // (group, chunk)), so a chunk read from L2 serves up to ZS groups.  Delays are
-// formed relative to the column centre.
+// formed relative to the column centre.  The per-transmit delay terms (and
+// transmit weights) of a group of QN transmits live in LDS (bq_lds: QN x 64
+// lanes x ZS floats per wavefront, each lane reading only its own entries),
+// which keeps them out of the register budget of the chunk loop.
 template <class S, int ZS, int NB, int QN, bool WTX>
 __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ ws, int B, int TW,
                                            int Kc, float* __restrict__ x, int ngx, int ngy,
-                                           int col, int by) {
+                                           int col, int by, float* __restrict__ bq_lds) {
   using T = typename Operand<S>::T;
   constexpr int NCH = ZS / 2 + 2;  // chunks loaded per step before the rare second pass
   const int lane = threadIdx.x & 63;
@@ -209,8 +212,10 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
     const int qn = min(QN, g.Q - q0);
     TxRef mine = {};
     if (lane < qn) mine = make_tx_ref(g, q0 + lane, px, py, pz);
-    float bq[QN][ZS], wq[WTX ? QN : 1][WTX ? ZS : 1];
-    int ktx[QN];
+    // per (transmit, lane): ZS delay terms and, with transmit weights, ZS weights
+    constexpr int PER = WTX ? 2 * ZS : ZS;
+    float* bql = bq_lds + (size_t)(threadIdx.x >> 6) * QN * 64 * PER + lane * PER;
+    const int my_ktx = mine.ktx;
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
       TxRef r;
@@ -219,13 +224,12 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
       r.vy = __shfl(mine.vy, q);
       r.vz = __shfl(mine.vz, q);
       r.vn = __shfl(mine.vn, q);
-      ktx[q] = __shfl(mine.ktx, q);
       const float gq = __shfl(mine.g, q);
 #pragma unroll
       for (int k = 0; k < ZS; ++k) {
-        bq[q][k] = fmaf(delta_tx(r, dx, dy, dz[k], dp2[k]), fscf, gq);
+        bql[q * 64 * PER + k] = fmaf(delta_tx(r, dx, dy, dz[k], dp2[k]), fscf, gq);
         if constexpr (WTX)
-          wq[q][k] = (q < qn && ink[k]) ? g.w_tx[(size_t)(q0 + q) * N + nk[k]] : 0.f;
+          bql[q * 64 * PER + ZS + k] = (q < qn && ink[k]) ? g.w_tx[(size_t)(q0 + q) * N + nk[k]] : 0.f;
       }
     }
     for (int m0 = 0; m0 < M; m0 += 64) {
@@ -282,19 +286,26 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
         }
         if (__ballot(anyw) == 0ull) continue;
         const S* cq = wtile + (size_t)q0 * q_el + (size_t)m * chan_el;
-#pragma unroll
+#pragma unroll 1
         for (int q = 0; q < QN; ++q) {
           const bool live = q < qn;
           int t[ZS];
           uint32_t P[ZS], Plo[ZS];
           int lo = BIG, hi = -BIG;
+          float bqv[ZS], wqv[ZS];
 #pragma unroll
           for (int k = 0; k < ZS; ++k) {
-            const float f = a[k] + bq[q][k];
-            t[k] = ktx[q] + krx + floor_i32(f);
+            bqv[k] = bql[q * 64 * PER + k];
+            wqv[k] = WTX ? bql[q * 64 * PER + ZS + k] : 1.f;
+          }
+          const int ktxq = __builtin_amdgcn_readlane(my_ktx, q);
+#pragma unroll
+          for (int k = 0; k < ZS; ++k) {
+            const float f = a[k] + bqv[k];
+            t[k] = ktxq + krx + floor_i32(f);
             const float al = frac_f32(f);
             const bool valid = live && w[k] != 0.f && t[k] >= -1 && t[k] <= K - 1;
-            const float wt = valid ? (WTX ? w[k] * wq[WTX ? q : 0][WTX ? k : 0] : w[k]) : 0.f;
+            const float wt = valid ? (WTX ? w[k] * wqv[k] : w[k]) : 0.f;
             const float w2 = wt * al, w1 = wt - w2;
             P[k] = Mma<T>::pack(w1, w2);
             Plo[k] = 0;
@@ -392,12 +403,13 @@ __device__ inline int xcd_remap(int b, int nblocks) {
 }
 
 template <class T, int ZS, int NB, int QN, bool WTX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward_stack(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 2 : 3))) void mfma_forward_stack(
     Geom g, const T* __restrict__ ws, int B, int TW, int Kc, float* __restrict__ x, int ngx,
     int ngy, int ncols) {
+  __shared__ __align__(16) float bq_lds[4 * QN * 64 * ZS * (WTX ? 2 : 1)];
   const int col = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (col >= ncols) return;  // whole wavefront
-  stack_body<T, ZS, NB, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y);
+  stack_body<T, ZS, NB, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y, bq_lds);
 }
 
 // Voxel groups per wavefront column of the depth-stacked form.
@@ -419,9 +431,10 @@ __global__ void zero_counters(unsigned* c) {
   if (threadIdx.x < kXcds) c[threadIdx.x] = 0u;
 }
 
-template <class T, int QN, bool WTX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void mfma_forward_batched(
+template <class T, int QN, bool WTX, int NBMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBMAX == 4 ? 2 : 3))) void mfma_forward_batched(
     MfmaBatchedArgs a, unsigned* __restrict__ ctr) {
+  __shared__ __align__(16) float bq_lds[4 * QN * 64 * kStack * (WTX ? 2 : 1)];
   const long long total = a.first[a.count];
   const unsigned xcd = blockIdx.x % kXcds;  // workgroups are dealt round-robin to the XCDs
   for (;;) {
@@ -438,14 +451,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void m
     const MfmaWork w = a.p[i];
     const int local = item - a.first[i];
     const int col = local % w.ngroups, by = local / w.ngroups;
-    // each plan runs with its own batch tiles per wavefront (w.nb, uniform),
-    // exactly as a single-plan launch would
-    if (w.nb == 2)
-      stack_body<T, kStack, 2, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
-                                        w.ngx, w.ngy, col, by);
+    // each plan runs with its own batch tiles per wavefront (w.nb, uniform:
+    // NBMAX or 1)
+    if (w.nb == NBMAX)
+      stack_body<T, kStack, NBMAX, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc,
+                                            w.x, w.ngx, w.ngy, col, by, bq_lds);
     else
       stack_body<T, kStack, 1, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
-                                        w.ngx, w.ngy, col, by);
+                                        w.ngx, w.ngy, col, by, bq_lds);
   }
 }
 
@@ -535,13 +548,14 @@ hipError_t launch_stack(const Geom& g, const void* ws, int B, float* x, hipStrea
 
 template <class T>
 hipError_t launch_any(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
+  if (mfma_stack_tiles(B) == 4) return launch_stack<T, kStack, 4>(g, ws, B, x, st);
   if (mfma_stack_tiles(B) == 2) return launch_stack<T, kStack, 2>(g, ws, B, x, st);
   return launch_stack<T, kStack, 1>(g, ws, B, x, st);
 }
 
-template <class T, int QN, bool WTX>
+template <class T, int QN, bool WTX, int NBMAX>
 hipError_t batched_t(const MfmaBatchedArgs& a, unsigned* ctr, int cus, hipStream_t st) {
-  auto kern = mfma_forward_batched<T, QN, WTX>;
+  auto kern = mfma_forward_batched<T, QN, WTX, NBMAX>;
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
   if (e != hipSuccess) return e;
@@ -558,21 +572,37 @@ hipError_t batched_t(const MfmaBatchedArgs& a, unsigned* ctr, int cus, hipStream
   return hipGetLastError();
 }
 
-template <class T>
+template <class T, int NBMAX>
 hipError_t batched_any(const MfmaBatchedArgs& a, unsigned* ctr, int qn, bool wtx, int cus,
                        hipStream_t st) {
   constexpr int QMAX = kStack >= 8 ? 4 : 8;
   if (qn == 1)
-    return wtx ? batched_t<T, 1, true>(a, ctr, cus, st) : batched_t<T, 1, false>(a, ctr, cus, st);
+    return wtx ? batched_t<T, 1, true, NBMAX>(a, ctr, cus, st)
+               : batched_t<T, 1, false, NBMAX>(a, ctr, cus, st);
   if (qn <= 4)
-    return wtx ? batched_t<T, 4, true>(a, ctr, cus, st) : batched_t<T, 4, false>(a, ctr, cus, st);
-  return wtx ? batched_t<T, QMAX, true>(a, ctr, cus, st) : batched_t<T, QMAX, false>(a, ctr, cus, st);
+    return wtx ? batched_t<T, 4, true, NBMAX>(a, ctr, cus, st)
+               : batched_t<T, 4, false, NBMAX>(a, ctr, cus, st);
+  return wtx ? batched_t<T, QMAX, true, NBMAX>(a, ctr, cus, st)
+             : batched_t<T, QMAX, false, NBMAX>(a, ctr, cus, st);
+}
+
+// Largest batch tiles per wavefront in a persistent launch.  FP8 fragments are
+// half the registers of 16-bit ones, so the four-tile body fits without spills
+// next to the one-tile body; the 16-bit types keep the two-tile body (and
+// three wavefronts per SIMD), which measured faster for them in this kernel.
+int batched_nbmax(int storage) { return storage == DAS_STORE_FP8_E4M3 ? 4 : 2; }
+
+// Batch tiles per wavefront of a plan in a persistent launch: the kernel's
+// NBMAX body or the one-tile body.
+int persistent_nb(int storage, int B) {
+  const int nbmax = batched_nbmax(storage), tiles = mfma_stack_tiles(B);
+  return tiles >= nbmax ? nbmax : nbmax == 2 ? tiles : 1;
 }
 
 }  // namespace
 
 int mfma_tiles_per_wave(int B) { return B > 32 ? 4 : B > 16 ? 2 : 1; }
-int mfma_stack_tiles(int B) { return std::min(2, mfma_tiles_per_wave(B)); }
+int mfma_stack_tiles(int B) { return mfma_tiles_per_wave(B); }
 int mfma_tile_width(int B) { return 16 * mfma_tiles_per_wave(B); }
 int mfma_batch_pad(int B) {
   const int tw = mfma_tile_width(B);
@@ -580,6 +610,16 @@ int mfma_batch_pad(int B) {
 }
 
 size_t mfma_batched_counter_bytes() { return kXcds * sizeof(unsigned); }
+
+// A single plan runs faster through the persistent kernel (dynamic balance of
+// the depth-dependent work) when that kernel gives it the same batch tiles per
+// wavefront as the stack launch at the same occupancy: always for the 16-bit
+// types up to two tiles; for FP8 only with four tiles (its one-tile body in
+// the four-tile kernel runs at two wavefronts per SIMD instead of three).
+bool mfma_prefers_persistent(int storage, int B) {
+  const int nbmax = batched_nbmax(storage), tiles = mfma_stack_tiles(B);
+  return nbmax == 2 ? tiles <= 2 : tiles == nbmax;
+}
 
 hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, int cus,
                                hipStream_t st) {
@@ -595,12 +635,12 @@ hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, i
     w.ngy = (w.g.n[1] + 3) / 4;
     w.ngroups = w.ngx * w.ngy * ((w.g.n[2] + kStack - 1) / kStack);  // wavefront columns
     w.nbx = 0;
-    w.nb = mfma_stack_tiles(w.B);
+    w.nb = persistent_nb(storage, w.B);
     a.first[i + 1] = a.first[i] + w.ngroups * (mfma_batch_pad(w.B) / (16 * w.nb));
   }
-  if (storage == DAS_STORE_F16) return batched_any<_Float16>(a, ctr, qn, wtx, cus, st);
-  if (storage == DAS_STORE_FP8_E4M3) return batched_any<uint8_t>(a, ctr, qn, wtx, cus, st);
-  return batched_any<uint16_t>(a, ctr, qn, wtx, cus, st);
+  if (storage == DAS_STORE_F16) return batched_any<_Float16, 2>(a, ctr, qn, wtx, cus, st);
+  if (storage == DAS_STORE_FP8_E4M3) return batched_any<uint8_t, 4>(a, ctr, qn, wtx, cus, st);
+  return batched_any<uint16_t, 2>(a, ctr, qn, wtx, cus, st);
 }
 int mfma_chunks(int K) { return (K + CH - 1) / CH + 2; }
 

@@ -24,8 +24,11 @@ def _block_around(g, pos, half=8):
     return synth.sub_grid(g, start, (2 * half, 2 * half, 2 * half))
 
 
+# FP8 bars: the oracle alone, beamforming the FP8-rounded lanes, is 1.32 dB
+# (max) and 0.151 dB (mean) off the FP64 envelope on this block (peak 0.13 um,
+# widths 0.18 um); the bars leave twice that.
 @pytest.mark.parametrize("storage,max_db,mean_db", [("f32", 0.002, 0.0002), ("f16", 0.05, 0.005),
-                                                    ("bf16", 0.4, 0.04)])
+                                                    ("bf16", 0.4, 0.04), ("fp8", 2.6, 0.3)])
 def test_envelope_and_point_targets_cfg2(gpu, storage, max_db, mean_db):
     """Envelope-dB error (voxels within 40 dB of the peak) and point-target
     peak / -6 dB widths of the precision forms vs the oracle, on a 16^3 block

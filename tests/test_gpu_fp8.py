@@ -142,3 +142,26 @@ def test_fp8_cfg2_full_volume_sampled(gpu, algo, B):
     for i, b in enumerate(items):
         check_close(x[i][idx], xo[i], *lowp_bars("fp8"), f"item {b}, sampled voxels")
         check_close(x[i][idx], xr[i], *KERNEL[algo], "  oracle on fp8-rounded data")
+
+
+def test_mfma_launches_overlapping_on_two_streams(gpu):
+    """Persistent MFMA forwards of one plan enqueued on two streams at once
+    take different counter sets: both equal a lone launch bit for bit."""
+    das = _das()
+    g = _geometry()
+    B = 40
+    plan = das.Plan(g, max_batch=B, storage="fp8")
+    ws = plan.prepare(_items(g, B, seed=90).to(gpu))
+    ref = plan.forward_ws(ws, B)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for r in range(3):
+        for s in (s1, s2):
+            with torch.cuda.stream(s):
+                x = torch.full_like(ref, float("nan"))
+                das.das_forward(plan.handle, ws, B, x)  # on the current stream s
+                outs.append(x)
+    torch.cuda.synchronize()
+    for x in outs:
+        assert torch.equal(x, ref)
