@@ -216,6 +216,9 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
     constexpr int PER = WTX ? 2 * ZS : ZS;
     float* bql = bq_lds + (size_t)(threadIdx.x >> 6) * QN * 64 * PER + lane * PER;
     const int my_ktx = mine.ktx;
+    // transmits of the group with a nonzero weight somewhere in this column
+    // (sparse transmit lists, Sec. 5: the others contribute exact zeros)
+    uint32_t qact = (1u << qn) - 1u;
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
       TxRef r;
@@ -225,12 +228,17 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
       r.vz = __shfl(mine.vz, q);
       r.vn = __shfl(mine.vn, q);
       const float gq = __shfl(mine.g, q);
+      bool nz = false;
 #pragma unroll
       for (int k = 0; k < ZS; ++k) {
         bql[q * 64 * PER + k] = fmaf(delta_tx(r, dx, dy, dz[k], dp2[k]), fscf, gq);
-        if constexpr (WTX)
-          bql[q * 64 * PER + ZS + k] = (q < qn && ink[k]) ? g.w_tx[(size_t)(q0 + q) * N + nk[k]] : 0.f;
+        if constexpr (WTX) {
+          const float wt = (q < qn && ink[k]) ? g.w_tx[(size_t)(q0 + q) * N + nk[k]] : 0.f;
+          bql[q * 64 * PER + ZS + k] = wt;
+          nz |= wt != 0.f;
+        }
       }
+      if (WTX && __ballot(nz) == 0ull) qact &= ~(1u << q);
     }
     for (int m0 = 0; m0 < M; m0 += 64) {
       const int me = m0 + lane;
@@ -288,6 +296,7 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
         const S* cq = wtile + (size_t)q0 * q_el + (size_t)m * chan_el;
 #pragma unroll 1
         for (int q = 0; q < QN; ++q) {
+          if (!((qact >> q) & 1u)) continue;  // wavefront-uniform
           const bool live = q < qn;
           int t[ZS];
           uint32_t P[ZS], Plo[ZS];

@@ -124,8 +124,9 @@ struct Stage {
 
 template <class T, int BT, int QN, int MC>
 __device__ inline void stage_load(Stage<BT, QN, MC>& st, const T* __restrict__ ws, const int* ktx,
-                                  const int* ek, const int* em, int c0, int q0, int qn, int mcn,
-                                  int M, int K, int B, int b0, int W, int dint, int wave, int lane) {
+                                  const int* ek, const int* em, const int* txl, int c0, int q0,
+                                  int qn, int mcn, int M, int K, int B, int b0, int W, int dint,
+                                  int wave, int lane) {
   constexpr int WPW = Stage<BT, QN, MC>::WPW;
 #pragma unroll
   for (int k = 0; k < WPW; ++k) {
@@ -139,7 +140,8 @@ __device__ inline void stage_load(Stage<BT, QN, MC>& st, const T* __restrict__ w
       const int krx = __builtin_amdgcn_readfirstlane(ek[e]);
       const int m = __builtin_amdgcn_readfirstlane(em[e]) & 0xffff;
       const int j0 = __builtin_amdgcn_readfirstlane(ktx[q]) + krx - dint;
-      const T* chan = ws + ((size_t)(q0 + q) * M + m) * (size_t)K * B + b0;
+      const int qt = txl ? __builtin_amdgcn_readfirstlane(txl[q0 + q]) : q0 + q;  // transmit
+      const T* chan = ws + ((size_t)qt * M + m) * (size_t)K * B + b0;
       const int j = j0 + lane;
       if (lane < W && j >= 0 && j < K) {
 #pragma unroll
@@ -173,7 +175,7 @@ template <class T, int BT, int QN, bool WTX>
 __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Window& win,
                                  const T* __restrict__ ws, int B, float* __restrict__ x, int ntx,
                                  int nty, int ntiles, int tile, int b0, unsigned char* smem,
-                                 int* ktx_s) {
+                                 int* ktx_s, int* txl_s) {
   constexpr int MC = chunk_elems<BT, QN>();
   const int W = win.pairs + 1;  // samples per window
   const Layout L = layout(QN, MC, BT, W);
@@ -234,6 +236,38 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
 #pragma unroll
   for (int b = 0; b < BT; ++b) acc[b] = 0.f;
 
+  // Sparse transmit list (the paper's sparse observation lists, Sec. 5): with
+  // transmit weights and Q <= 64 the tile loops only over the transmits whose
+  // weight is nonzero somewhere in it (txl_s[0 .. nq-1]); every term skipped
+  // is an exact zero, so the result does not change.
+  int nq = g.Q;
+  const int* txl = nullptr;
+  if (WTX && g.Q <= 64) {
+    uint64_t mine = 0;
+    if (inside)
+      for (int q = 0; q < g.Q; ++q)
+        if (g.w_tx[(size_t)q * N + n] != 0.f) mine |= 1ull << q;
+    uint32_t lo = (uint32_t)mine, hi = (uint32_t)(mine >> 32);
+    for (int o = 32; o > 0; o >>= 1) {
+      lo |= (uint32_t)__shfl_xor((int)lo, o);
+      hi |= (uint32_t)__shfl_xor((int)hi, o);
+    }
+    __syncthreads();  // txl_s is free (a previous tile of a persistent launch is done)
+    if (lane == 0) {
+      txl_s[64 + 2 * wave] = (int)lo;
+      txl_s[65 + 2 * wave] = (int)hi;
+    }
+    __syncthreads();
+    uint64_t all = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      all |= (uint64_t)(uint32_t)txl_s[64 + 2 * w] | ((uint64_t)(uint32_t)txl_s[65 + 2 * w] << 32);
+    if (t < g.Q && ((all >> t) & 1ull)) txl_s[__popcll(all & ((1ull << t) - 1ull))] = t;
+    nq = __popcll(all);
+    txl = txl_s;
+    // the list is published by the barrier at the start of the transmit-group loop
+  }
+
   int mscan = 0;
   while (mscan < M) {
     // ---- compact the next batch of elements that can reach this tile ----
@@ -289,11 +323,11 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
       __syncthreads();
     }
 
-    for (int q0 = 0; q0 < g.Q; q0 += QN) {
-      const int qn = min(QN, g.Q - q0);
+    for (int q0 = 0; q0 < nq; q0 += QN) {
+      const int qn = min(QN, nq - q0);
       __syncthreads();
       if (t < qn) {
-        const TxRef r = make_tx_ref(g, q0 + t, px, py, pz);
+        const TxRef r = make_tx_ref(g, txl ? txl[q0 + t] : q0 + t, px, py, pz);
         qinfo[t] = QInfo{r.vx, r.vy, r.vz, r.vn, r.g, r.ktx, r.kind, 0};
         ktx_s[t] = r.ktx;
       }
@@ -309,22 +343,23 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           TxRef r;
           r.vx = qi.vx; r.vy = qi.vy; r.vz = qi.vz; r.vn = qi.vn; r.kind = qi.kind;
           bq[q] = fmaf(delta_tx(r, dx, dy, dz, dp2), fscf, qi.g);
-          if (WTX) wq[WTX ? q : 0] = !inside ? 0.f : g.w_tx ? g.w_tx[(size_t)(q0 + q) * N + n] : 1.f;
+          if (WTX)
+            wq[WTX ? q : 0] = !inside ? 0.f : g.w_tx[(size_t)(txl ? txl[q0 + q] : q0 + q) * N + n];
         }
       }
 
       Stage<BT, QN, MC> st;
       if (nact > 0)
-        stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, 0, q0, qn, min(MC, nact), M, K, B, b0, W,
-                                  win.dint, wave, lane);
+        stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, txl, 0, q0, qn, min(MC, nact), M, K, B,
+                                  b0, W, win.dint, wave, lane);
       for (int c0 = 0; c0 < nact; c0 += MC) {
         const int mcn = min(MC, nact - c0);
         __syncthreads();  // the previous chunk is no longer read
         stage_store<BT, QN, MC>(st, wsm, mcn, W, wave, lane);
         __syncthreads();
         if (c0 + MC < nact)
-          stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, c0 + MC, q0, qn, min(MC, nact - c0 - MC),
-                                    M, K, B, b0, W, win.dint, wave, lane);
+          stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, txl, c0 + MC, q0, qn,
+                                    min(MC, nact - c0 - MC), M, K, B, b0, W, win.dint, wave, lane);
         // ---- interpolate and accumulate ----
         for (int mc = 0; mc < mcn; ++mc) {
           const int e = c0 + mc;
@@ -344,6 +379,9 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           constexpr int QR = QN * BT <= 8 ? QN : (8 / BT < 1 ? 1 : 8 / BT);
 #pragma unroll
           for (int qa = 0; qa < QN; qa += QR) {
+            // with transmit weights the group may be short (sparse list): stop
+            // at its last transmit (block-uniform)
+            if (WTX && qa >= qn) break;
             float s1[QR][BT], s2[QR][BT], al[QR];
 #pragma unroll
             for (int r = 0; r < QR; ++r) {
@@ -387,6 +425,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ti
     int ntx, int nty, int ntiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int ktx_s[16];
+  __shared__ int txl_s[72];  // sparse transmit list (64) + per-wavefront masks (8)
   // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs (each
   // with its own L2); give every XCD runs of 16 consecutive tiles (neighbours
   // that stage overlapping sample windows), runs interleaved across XCDs so
@@ -396,7 +435,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ti
   const int bx = (int)blockIdx.x;
   const int tile = bx >= (int)gridDim.x / per * per ? bx : bx / per * per + (bx % per % X) * C + (bx % per) / X;
   tile_body<T, BT, QN, WTX>(g, ts, win, ws, B, x, ntx, nty, ntiles, tile, blockIdx.y * BT, smem,
-                            ktx_s);
+                            ktx_s, txl_s);
 }
 
 // Several forward passes in one persistent launch: in round r, workgroup w
@@ -410,6 +449,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void ti
     BatchedArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int ktx_s[16];
+  __shared__ int txl_s[72];  // sparse transmit list (64) + per-wavefront masks (8)
   const int total = a.first[a.count];
   const unsigned G = gridDim.x;
   for (int r = 0; r * (int)G < total; ++r) {
@@ -424,7 +464,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void ti
     const int tile = local % w.ntiles, bg = local / w.ntiles;
     __syncthreads();  // the previous item no longer reads LDS
     tile_body<T, BT, QN, WTX>(w.g, w.ts, w.win, static_cast<const T*>(w.ws), w.B, w.x, w.ntx,
-                              w.nty, w.ntiles, tile, bg * BT, smem, ktx_s);
+                              w.nty, w.ntiles, tile, bg * BT, smem, ktx_s, txl_s);
   }
 }
 

@@ -316,3 +316,39 @@ def random_channel_data(g: Geometry, batch: int, seed: int, device="cpu"):
     import torch
     gen = torch.Generator(device="cpu").manual_seed(seed)
     return torch.randn(batch, g.Q, g.M, g.K, generator=gen).to(device)
+
+
+def selective_tx_weights(g: Geometry, grid=None, overlap: float = 0.5, taper: float = 0.25):
+    """Transmit weights w_tx[Q, N] float32 of a spatially selective sequence:
+    the Q transmits are laid out on a lateral a x b grid (a b = Q; default the
+    most square factorisation) and transmit (i, j) weighs only voxels whose
+    lateral position falls inside its cell widened by `overlap` (fraction of a
+    cell on each side), with a raised-cosine taper over the outer `taper`
+    fraction of that box and exactly zero outside it.  An input pattern, not
+    part of the beamformer: the forward treats it as any other w_tx."""
+    Q = g.Q
+    if grid is None:
+        a = int(np.floor(np.sqrt(Q)))
+        while Q % a:
+            a -= 1
+        grid = (Q // a, a)
+    ga, gb = grid
+    assert ga * gb == Q
+    nx, ny, nz = g.grid_dims
+    x = np.arange(nx) / max(nx - 1, 1)          # lateral position in [0, 1]
+    y = np.arange(ny) / max(ny - 1, 1)
+
+    def profile(u, cells, i):
+        c0, c1 = i / cells, (i + 1) / cells
+        half = 0.5 * (c1 - c0) * (1.0 + 2.0 * overlap)
+        mid = 0.5 * (c0 + c1)
+        d = np.abs(u - mid) / half                # 0 at the centre, 1 at the box edge
+        w = np.where(d <= 1.0 - taper, 1.0,
+                     np.where(d < 1.0, 0.5 * (1.0 + np.cos(np.pi * (d - (1.0 - taper)) / taper)), 0.0))
+        return w
+
+    w = np.empty((Q, nz, ny, nx), np.float32)
+    for q in range(Q):
+        i, j = q % ga, q // ga
+        w[q] = (profile(y, gb, j)[:, None] * profile(x, ga, i)[None, :])[None, :, :]
+    return w.reshape(Q, -1)
