@@ -352,3 +352,36 @@ def selective_tx_weights(g: Geometry, grid=None, overlap: float = 0.5, taper: fl
         i, j = q % ga, q // ga
         w[q] = (profile(y, gb, j)[:, None] * profile(x, ga, i)[None, :])[None, :, :]
     return w.reshape(Q, -1)
+
+
+def doppler_ensemble(shape=(32, 24, 16), T: int = 64, seed: int = 0, n_clutter: int = 3,
+                     clutter_amp: float = 100.0, blood_amp: float = 1.0, noise: float = 0.1,
+                     rho: float = 0.9):
+    """A synthetic beamformed Doppler ensemble x[T, N] float32 (N = prod(shape),
+    n = ix + nx (iy + ny iz)): tissue clutter of rank n_clutter (smooth spatial
+    patterns times slow temporal modulations, amplitude clutter_amp), blood
+    inside a tube through the volume (AR(1) in time with coefficient rho,
+    amplitude blood_amp) and white noise.  An input pattern only."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    t = np.arange(T) / T
+    x = np.zeros((T, N))
+    for c in range(n_clutter):
+        k = rng.uniform(0.5, 2.0, 3)
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        spatial = (np.cos(2 * np.pi * k[0] * ix / nx + ph[0]) * np.cos(2 * np.pi * k[1] * iy / ny + ph[1])
+                   * np.cos(2 * np.pi * k[2] * iz / nz + ph[2])).ravel()
+        temporal = 1.0 + 0.3 * np.cos(2 * np.pi * (c + 0.5) * t + rng.uniform(0, 2 * np.pi))
+        x += clutter_amp * (0.6 ** c) * temporal[:, None] * spatial[None, :]
+    # blood: a tube along z at (nx/2, ny/3), radius ~ nx/6
+    vessel = ((ix - nx / 2) ** 2 + (iy - ny / 3) ** 2 <= (nx / 6) ** 2).ravel()
+    nb = int(vessel.sum())
+    b = np.zeros((T, nb))
+    b[0] = rng.normal(0, 1, nb)
+    for i in range(1, T):
+        b[i] = rho * b[i - 1] + np.sqrt(1 - rho ** 2) * rng.normal(0, 1, nb)
+    x[:, vessel] += blood_amp * b
+    x += noise * rng.normal(0, 1, (T, N))
+    return x.astype(np.float32), vessel
