@@ -218,6 +218,28 @@ das_status das_tile_shape(int32_t tile_index, int32_t dims[3]);
 das_status das_debug_delays(das_plan p, int32_t q, int32_t m0, int32_t m1, int32_t n0, int32_t n1,
                             double* f_out, void* stream);
 
+/* Rank-truncation (SVD) clutter filter and power Doppler of an ensemble: the
+ * rank-truncation primitive the paper names beside the beamformer (Sec. 1,
+ * Sec. 6).  x: device [T][N] f32, T frames of N voxels (for example the
+ * output of das_forward for a batch of T frames), read as the Casorati matrix
+ * S = x^T = U diag(sigma) V^T.  The filter keeps the singular components
+ * k_lo .. k_hi-1 (0 <= k_lo < k_hi <= T; the k_lo largest are tissue
+ * clutter, components from k_hi on are noise):
+ *   xf = sum_{k_lo <= j < k_hi} sigma_j v_j-projection of each voxel series,
+ *   power[n] = (1/T) sum_t xf[t][n]^2.
+ * Outputs (device, caller-owned): sv[T] f32 singular values, descending;
+ * power[N] f32; xf[T][N] f32 or NULL.  ws: device workspace of
+ * das_clutter_workspace_bytes(T) bytes, caller-owned (not kept between
+ * calls).  Requirements: 1 <= T <= 512, N >= 1, and the smaller of
+ * (k_hi - k_lo) and T - (k_hi - k_lo) at most 64 (DAS_ERR_UNSUPPORTED
+ * otherwise; DAS_ERR_INVALID_ARG for bad sizes or NULL pointers).
+ * Method: Gram matrix x x^T on the matrix cores (FP32, chunks merged in
+ * FP64), FP64 parallel Jacobi eigen-decomposition, per-voxel projection.
+ * Runs on the calling thread's current device. */
+das_status das_clutter_workspace_bytes(int32_t T, size_t* bytes);
+das_status das_clutter_filter(const float* x, int32_t T, int64_t N, int32_t k_lo, int32_t k_hi,
+                              float* sv, float* power, float* xf, void* ws, void* stream);
+
 const char* das_status_string(das_status st);
 const char* das_last_error(void);
 /* Library version string. */

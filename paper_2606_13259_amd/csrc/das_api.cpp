@@ -664,6 +664,32 @@ das_status das_autotune(das_plan p, int32_t batch, void* stream) {
   return DAS_OK;
 }
 
+das_status das_clutter_workspace_bytes(int32_t T, size_t* bytes) {
+  if (!bytes) return fail(DAS_ERR_INVALID_ARG, "bytes is NULL");
+  if (T < 1 || T > 512) return fail(DAS_ERR_INVALID_ARG, "T must be in [1, 512]");
+  *bytes = clutter_workspace_bytes(T);
+  return DAS_OK;
+}
+
+das_status das_clutter_filter(const float* x, int32_t T, int64_t N, int32_t k_lo, int32_t k_hi,
+                              float* sv, float* power, float* xf, void* ws, void* stream) {
+  if (!x || !sv || !power || !ws) return fail(DAS_ERR_INVALID_ARG, "x, sv, power or ws is NULL");
+  if (T < 1 || T > 512) return fail(DAS_ERR_INVALID_ARG, "T must be in [1, 512]");
+  if (N < 1) return fail(DAS_ERR_INVALID_ARG, "N must be >= 1");
+  if (k_lo < 0 || k_hi <= k_lo || k_hi > T)
+    return fail(DAS_ERR_INVALID_ARG, "need 0 <= k_lo < k_hi <= T");
+  if (clutter_basis_size(T, k_lo, k_hi) > 64)
+    return fail(DAS_ERR_UNSUPPORTED, "at most 64 components may be kept or removed");
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = launch_clutter_filter(x, T, N, k_lo, k_hi, sv, power, xf, ws, cus,
+                            static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "das_clutter_filter launch");
+  return DAS_OK;
+}
+
 das_status das_debug_delays(das_plan p, int32_t q, int32_t m0, int32_t m1, int32_t n0, int32_t n1,
                             double* f_out, void* stream) {
   if (das_status s = check_plan(p)) return s;

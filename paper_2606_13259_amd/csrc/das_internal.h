@@ -136,6 +136,12 @@ size_t tiled_lds_f16(const Geom& g, int bt, const Window& w);
 size_t tiled_lds_bf16(const Geom& g, int bt, const Window& w);
 size_t tiled_lds_fp8(const Geom& g, int bt, const Window& w);
 
+// Rank-truncation clutter filter (k_clutter.hip).
+size_t clutter_workspace_bytes(int T);
+int clutter_basis_size(int T, int k_lo, int k_hi);  // components the projection uses
+hipError_t launch_clutter_filter(const float* x, int T, long long N, int k_lo, int k_hi, float* sv,
+                                 float* pd, float* xf, void* ws, int cus, hipStream_t st);
+
 // LDS bytes the tiled forward kernel needs (0 if it cannot run this shape).
 size_t tiled_lds_bytes(const Geom& g, int storage, int bt, const Window& w);
 int tiled_batch_per_thread(int storage, int B);

@@ -99,6 +99,8 @@ def lib():
             "das_plan_set_tile": [_P, _I],
             "das_tile_shape": [_I, ctypes.POINTER(_I)],
             "das_debug_delays": [_P, _I, _I, _I, _I, _I, _P, _P],
+            "das_clutter_workspace_bytes": [_I, ctypes.POINTER(ctypes.c_size_t)],
+            "das_clutter_filter": [_P, _I, ctypes.c_int64, _I, _I, _P, _P, _P, _P, _P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -213,6 +215,37 @@ def das_forward_batched(plans, ws_list, batches, xs):
 
 def das_autotune(h, batch: int, device):
     _check(lib().das_autotune(h, int(batch), _stream(device)), "das_autotune")
+
+
+def das_clutter_workspace_bytes(T: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().das_clutter_workspace_bytes(int(T), ctypes.byref(n)), "das_clutter_workspace_bytes")
+    return n.value
+
+
+def das_clutter_filter(x: torch.Tensor, k_lo: int, k_hi: int, sv: torch.Tensor, power: torch.Tensor,
+                       xf: Optional[torch.Tensor], ws: torch.Tensor):
+    T = x.shape[0]
+    N = x.numel() // T
+    _check(lib().das_clutter_filter(_ptr(x), int(T), int(N), int(k_lo), int(k_hi), _ptr(sv), _ptr(power),
+                                    _ptr(xf), _ptr(ws), _stream(x.device)), "das_clutter_filter")
+
+
+def clutter_filter(x: torch.Tensor, k_lo: int, k_hi: Optional[int] = None, filtered: bool = False):
+    """Rank-truncation clutter filter of an ensemble x[T, ...] (float32, on a
+    GPU): keeps singular components k_lo .. k_hi-1 of the Casorati matrix.
+    Returns (singular values [T], power Doppler [...], filtered ensemble or
+    None)."""
+    assert x.dtype == torch.float32 and x.is_contiguous() and x.is_cuda
+    T = x.shape[0]
+    k_hi = T if k_hi is None else k_hi
+    with torch.cuda.device(x.device):
+        ws = torch.empty(das_clutter_workspace_bytes(T), dtype=torch.uint8, device=x.device)
+        sv = torch.empty(T, dtype=torch.float32, device=x.device)
+        pw = torch.empty(x.shape[1:], dtype=torch.float32, device=x.device)
+        xf = torch.empty_like(x) if filtered else None
+        das_clutter_filter(x, k_lo, k_hi, sv, pw, xf, ws)
+    return sv, pw, xf
 
 
 def das_debug_delays(h, q, m0, m1, n0, n1, out: torch.Tensor):

@@ -91,3 +91,28 @@ def test_null_plan_and_pointers_are_rejected():
         assert L.das_tile_shape(i, dims) == das.DAS_OK
         assert dims[0] * dims[1] * dims[2] == 256
     assert L.das_tile_shape(99, dims) == das.DAS_ERR_INVALID_ARG
+
+
+def test_clutter_filter_argument_checks():
+    """The clutter filter validates sizes, component ranges and pointers on
+    the host (no pointer is dereferenced before the checks pass)."""
+    das, L = _lib()
+    n = ctypes.c_size_t()
+    assert L.das_clutter_workspace_bytes(0, ctypes.byref(n)) == das.DAS_ERR_INVALID_ARG
+    assert L.das_clutter_workspace_bytes(513, ctypes.byref(n)) == das.DAS_ERR_INVALID_ARG
+    assert L.das_clutter_workspace_bytes(256, None) == das.DAS_ERR_INVALID_ARG
+    assert L.das_clutter_workspace_bytes(256, ctypes.byref(n)) == das.DAS_OK
+    assert n.value >= 2 * 256 * 256 * 8
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails its checks
+    cases = [
+        ((None, 64, 100, 3, 64), das.DAS_ERR_INVALID_ARG),     # x NULL
+        ((fake, 0, 100, 0, 1), das.DAS_ERR_INVALID_ARG),       # T = 0
+        ((fake, 64, 0, 3, 64), das.DAS_ERR_INVALID_ARG),       # N = 0
+        ((fake, 64, 100, 5, 5), das.DAS_ERR_INVALID_ARG),      # empty band
+        ((fake, 64, 100, 3, 65), das.DAS_ERR_INVALID_ARG),     # k_hi > T
+        ((fake, 64, 100, -1, 10), das.DAS_ERR_INVALID_ARG),    # k_lo < 0
+        ((fake, 256, 100, 100, 200), das.DAS_ERR_UNSUPPORTED),  # 100 kept, 156 removed: > 64
+    ]
+    for (x, T, N, lo, hi), want in cases:
+        st = L.das_clutter_filter(x, T, N, lo, hi, fake, fake, None, fake, None)
+        assert st == want, (T, N, lo, hi, st)

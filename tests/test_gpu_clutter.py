@@ -1,0 +1,135 @@
+"""SVD rank-truncation clutter filter and power Doppler on the MI355X against
+the FP64 oracle (oracle.clutter).
+
+Bars (derived from the arithmetic): the Gram matrix is formed from FP32
+products summed in FP32 over one voxel chunk (at most a few thousand
+64-voxel steps) and in FP64 across chunks, a relative error of order 1e-6 of
+its largest entry; the FP64 Jacobi adds nothing comparable.  By Weyl's
+inequality every eigenvalue sigma_i^2 is then within that error of
+sigma_1^2: bar |sigma_i^2 - sigma_o,i^2| <= 2e-5 sigma_1^2.  The filtered
+series depends on the kept subspace, whose angle error is the Gram error over
+the gap at the cut (the test ensembles have clear gaps there), and on FP32
+rounding of the removal form s - B a (relative 1e-7 of the clutter
+amplitude): bar rel-L2 <= 1e-4 on the power image.  For T <= 256 the
+eigen-solve runs in FP32 (in LDS) followed by one first-order FP64
+correction across the cuts, which leaves a rotation of order
+(2^-24 sigma_1^2 / gap)^2 at a cut: up to ~4e-3 at the noise-tail cut of the
+band test (sigma_1^2 = 1e6, gap ~1), weighted by that component's small
+share of the kept energy; the filtered series has the bar 1e-3.  Singular
+vectors have arbitrary signs, so only the singular values, the power image
+and the filtered series (all unique) are compared."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle.clutter import power_doppler, svd_filter
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+SIG2_BAR = 2e-5
+POWER_BAR = 1e-4
+XF_BAR = 1e-3
+
+
+def _das():
+    from paper_2606_13259_amd import das
+    return das
+
+
+def _check(x, k_lo, k_hi, gpu, what, filtered=True):
+    das = _das()
+    x = np.ascontiguousarray(x)
+    sv, pw, xf = das.clutter_filter(torch.from_numpy(x).to(gpu), k_lo, k_hi, filtered=filtered)
+    sv, pw = sv.cpu().numpy().astype(np.float64), pw.cpu().numpy().reshape(-1).astype(np.float64)
+    so, po = power_doppler(x, k_lo, k_hi)
+    so = np.concatenate([so, np.zeros(x.shape[0] - so.size)])  # N < T: the rest are zero
+    e_sig = float(np.max(np.abs(sv ** 2 - so ** 2)) / so[0] ** 2)
+    # relative to the filtered power, or to the input power where the filter
+    # leaves (numerically) nothing
+    raw = np.mean(x.astype(np.float64) ** 2, 0)
+    den = np.linalg.norm(po) if np.linalg.norm(po) > 1e-6 * np.linalg.norm(raw) else np.linalg.norm(raw)
+    e_pw = float(np.linalg.norm(pw - po) / den)
+    say(f"  {what}: sigma^2 err {e_sig:.2e} (bar {SIG2_BAR:g}), power rel-L2 {e_pw:.2e} (bar {POWER_BAR:g})")
+    assert np.all(np.diff(sv) <= 0)
+    assert e_sig <= SIG2_BAR
+    assert e_pw <= POWER_BAR
+    if filtered:
+        xo = svd_filter(x, k_lo, k_hi)[1]
+        xg = xf.cpu().numpy().reshape(x.shape[0], -1).astype(np.float64)
+        # as for the power: relative to the input where the filter leaves
+        # (numerically) nothing (amplitudes: 1e-3, the square root of 1e-6)
+        nx, no = np.linalg.norm(x.astype(np.float64)), np.linalg.norm(xo)
+        e_xf = float(np.linalg.norm(xg - xo) / (no if no > 1e-3 * nx else nx))
+        say(f"    filtered series rel-L2 {e_xf:.2e} (bar {XF_BAR:g})")
+        assert e_xf <= XF_BAR
+    return sv, pw
+
+
+def _known(N=300, T=24, seed=0):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.normal(size=(N, T)))
+    V, _ = np.linalg.qr(rng.normal(size=(T, T)))
+    s = np.logspace(2, 0, T) * rng.uniform(0.9, 1.1, T)
+    s = np.sort(s)[::-1]
+    return ((U * s) @ V.T).T.astype(np.float32), U, s
+
+
+@pytest.mark.parametrize("k_lo,k_hi", [(3, 24), (0, 24), (3, 20), (20, 24), (0, 1)])
+def test_known_decomposition(gpu, k_lo, k_hi):
+    """Chosen U, V, sigma: keep and removal forms, both ends of the band."""
+    x, U, s = _known()
+    _check(x, k_lo, k_hi, gpu, f"known SVD, keep {k_lo}..{k_hi}")
+
+
+@pytest.mark.parametrize("shape,T,k_lo", [((16, 12, 8), 48, 3), ((32, 32, 32), 256, 3),
+                                         ((13, 7, 11), 67, 3)])
+def test_doppler_ensembles(gpu, shape, T, k_lo):
+    """Synthetic ensembles (rank-3 tissue clutter 40 dB above blood in a
+    vessel, noise); T = 67 and N = 1001 are not multiples of the 64-frame
+    Gram blocks or the 64-voxel steps."""
+    x, vessel = synth.doppler_ensemble(shape, T=T, seed=T)
+    say(f"ensemble {shape} T={T}")
+    sv, pw = _check(x, k_lo, T, gpu, f"remove {k_lo}", filtered=T <= 67)
+    assert np.median(pw[vessel]) > 20 * np.median(pw[~vessel])
+
+
+def test_band_with_noise_tail(gpu):
+    """Keep 3 .. T-4: 3 strong components and a weak 4-component tail
+    removed, with gaps at both cuts (T = 67, N = 1001, both ragged).  (With
+    no gap at a cut the kept subspace is not unique to the precision of the
+    data and only the singular values can be compared.)"""
+    rng = np.random.default_rng(9)
+    N, T = 1001, 67
+    U, _ = np.linalg.qr(rng.normal(size=(N, T)))
+    V, _ = np.linalg.qr(rng.normal(size=(T, T)))
+    # tissue ~40 dB above the blood band, a noise tail ~20 dB below it
+    s = np.concatenate([np.logspace(3, 2.6, 3), np.logspace(1, 0, T - 7), np.logspace(-1, -1.3, 4)])
+    x = ((U * s) @ V.T).T.astype(np.float32)
+    _check(x, 3, 63, gpu, "band 3..63")
+
+
+@pytest.mark.parametrize("T,N", [(1, 50), (2, 1), (64, 64), (65, 1)])
+def test_degenerate_sizes(gpu, T, N):
+    rng = np.random.default_rng(T + N)
+    x = rng.normal(size=(T, N)).astype(np.float32)
+    _check(x, 0, T, gpu, f"T={T} N={N} keep all")
+    if T > 1:
+        _check(x, 1, T, gpu, f"T={T} N={N} remove 1")
+
+
+def test_workspace_is_reused(gpu):
+    """Two calls on one workspace (the second smaller) agree with fresh ones."""
+    das = _das()
+    x1, _ = synth.doppler_ensemble((16, 12, 8), T=48, seed=1)
+    x2, _ = synth.doppler_ensemble((8, 8, 8), T=20, seed=2)
+    ws = torch.empty(das.das_clutter_workspace_bytes(48), dtype=torch.uint8, device=gpu)
+    for x in (x1, x2):
+        T = x.shape[0]
+        xt = torch.from_numpy(x).to(gpu)
+        sv = torch.empty(T, device=gpu)
+        pw = torch.empty(x.shape[1], device=gpu)
+        das.das_clutter_filter(xt, 3, T, sv, pw, None, ws)
+        sv2, pw2, _ = das.clutter_filter(xt, 3, T)
+        assert torch.equal(sv, sv2) and torch.equal(pw, pw2)
