@@ -281,6 +281,9 @@ __global__ __launch_bounds__(1024) void jacobi_lds(const double* __restrict__ G,
     if (i <= j) A[upk(T, i, j)] = (float)G[w];
   }
   __syncthreads();
+  __shared__ int rotated;
+  if (tid == 0) rotated = 0;
+  __syncthreads();
   int sweeps = 0;
   for (; sweeps < kMaxSweeps; ++sweeps) {
     for (int r = 0; r < Tp - 1; ++r) {
@@ -295,7 +298,8 @@ __global__ __launch_bounds__(1024) void jacobi_lds(const double* __restrict__ G,
         float c = 1.f, s = 0.f;
         if (q < T) {
           const float app = upl(A, T, p, p), aqq = upl(A, T, q, q), apq = upl(A, T, p, q);
-          if (apq != 0.f) {
+          if (fabsf(apq) > 1.1920929e-7f * sqrtf(fabsf(app * aqq))) {
+            rotated = 1;
             const float th = (aqq - app) / (2.f * apq);
             const float tt = (th >= 0.f ? 1.f : -1.f) / (fabsf(th) + sqrtf(th * th + 1.f));
             c = 1.f / sqrtf(tt * tt + 1.f);
@@ -363,10 +367,17 @@ __global__ __launch_bounds__(1024) void jacobi_lds(const double* __restrict__ G,
       dia += red[1][w];
     }
     __syncthreads();
-    if (off <= 1e-13f * dia) {
+    // converged: off-diagonal mass negligible, or a whole sweep without a
+    // rotation (every |a_pq| <= 2^-23 sqrt(a_pp a_qq): the relative
+    // criterion, which keeps refining the small eigenpairs)
+    const bool none = rotated == 0;
+    __syncthreads();
+    if (off <= 1e-13f * dia || none) {
       ++sweeps;
       break;
     }
+    if (tid == 0) rotated = 0;
+    __syncthreads();
   }
   for (int i = tid; i < T; i += nt) lam[i] = A[upk(T, i, i)];
   if (tid == 0) *nrot = sweeps * (Tp - 1) * np;
