@@ -385,3 +385,34 @@ def doppler_ensemble(shape=(32, 24, 16), T: int = 64, seed: int = 0, n_clutter: 
     x[:, vessel] += blood_amp * b
     x += noise * rng.normal(0, 1, (T, N))
     return x.astype(np.float32), vessel
+
+
+def doppler_ensemble_device(shape=(128, 128, 128), T: int = 256, seed: int = 0, n_clutter: int = 3,
+                            clutter_amp: float = 100.0, blood_amp: float = 1.0, noise: float = 0.1,
+                            rho: float = 0.9, device="cuda"):
+    """The recipe of doppler_ensemble generated with torch on a device (for
+    ensembles too large for the host path); returns x[T, N] float32."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    nx, ny, nz = shape
+    iz, iy, ix = torch.meshgrid(torch.arange(nz, device=device), torch.arange(ny, device=device),
+                                torch.arange(nx, device=device), indexing="ij")
+    t = torch.arange(T, device=device, dtype=torch.float32) / T
+    x = torch.zeros(T, nx * ny * nz, device=device)
+    for c in range(n_clutter):
+        k = torch.rand(3, generator=g) * 1.5 + 0.5
+        ph = torch.rand(4, generator=g) * 2 * np.pi
+        spatial = (torch.cos(2 * np.pi * float(k[0]) * ix / nx + float(ph[0]))
+                   * torch.cos(2 * np.pi * float(k[1]) * iy / ny + float(ph[1]))
+                   * torch.cos(2 * np.pi * float(k[2]) * iz / nz + float(ph[2]))).reshape(-1)
+        temporal = 1.0 + 0.3 * torch.cos(2 * np.pi * (c + 0.5) * t + float(ph[3]))
+        x += clutter_amp * (0.6 ** c) * temporal[:, None] * spatial[None, :]
+    vessel = ((ix - nx / 2) ** 2 + (iy - ny / 3) ** 2 <= (nx / 6) ** 2).reshape(-1)
+    nb = int(vessel.sum())
+    b = torch.randn(nb, generator=g).to(device)
+    for i in range(T):
+        if i:
+            b = rho * b + float(np.sqrt(1 - rho ** 2)) * torch.randn(nb, generator=g).to(device)
+        x[i, vessel] += blood_amp * b
+    x += noise * torch.randn(T, nx * ny * nz, generator=g).to(device)
+    return x.contiguous(), vessel
