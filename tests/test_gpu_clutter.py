@@ -133,3 +133,9 @@ def test_workspace_is_reused(gpu):
         das.das_clutter_filter(xt, 3, T, sv, pw, None, ws)
         sv2, pw2, _ = das.clutter_filter(xt, 3, T)
         assert torch.equal(sv, sv2) and torch.equal(pw, pw2)
+
+
+def test_more_than_256_frames(gpu):
+    """T = 300: the FP64 Jacobi on global memory (no LDS copy), same bars."""
+    x, vessel = synth.doppler_ensemble((12, 10, 8), T=300, seed=300)
+    _check(x, 3, 300, gpu, "T = 300, remove 3", filtered=True)
