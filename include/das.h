@@ -129,6 +129,17 @@ das_status das_plan_set_sound_speed(das_plan p, double c);
 /* Optional transmit weights w_tx[Q][N] f32 (device, caller-owned, must outlive
  * the calls that use it); NULL restores w_tx = 1. */
 das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
+/* Complex baseband (IQ) mode, the paper's data model (Sec. 2), with the phase
+ * term that Eq. (2) omits for demodulated data: with enable != 0 the batch
+ * items come in pairs (2b, 2b+1) = (I, Q) of one complex record, demodulated
+ * at the carrier fc (Hz, finite, >= 0): y_iq(t_k) = y_analytic(t_k)
+ * exp(-i 2 pi fc t_k), t_k = t0 + k/fs.  das_forward then writes
+ *   x[2b] + i x[2b+1] = sum_q sum_m w ((1-a) s(k) + a s(k+1)) exp(i 2 pi fc tau),
+ * tau = (D_tx + D_rx)/c, from the interpolated complex samples s.  Runs in the
+ * windowed algorithm with f32 storage and an even batch (DAS_ERR_UNSUPPORTED /
+ * DAS_ERR_INVALID_ARG otherwise); das_adjoint, das_grad_sound_speed and
+ * das_forward_batched refuse IQ plans.  enable = 0 restores real data. */
+das_status das_plan_set_iq(das_plan p, int32_t enable, double fc);
 /* Force an algorithm (das_algo) for subsequent calls; AUTO restores the
  * plan's choice.  AUTO depends only on the storage type, the batch size and
  * what was fixed at plan creation: MFMA for 16- or 8-bit storage with batch >= 16,

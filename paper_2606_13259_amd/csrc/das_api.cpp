@@ -125,6 +125,9 @@ struct das_plan_s {
   // plan creation so that the layout written by das_prepare and read by
   // das_forward never depends on later tile or sound-speed changes.
   bool auto_tiled = false;
+  // Complex baseband mode (das_plan_set_iq): carrier frequency (Hz).
+  bool iq = false;
+  double fc = 0.0;
 };
 
 namespace {
@@ -151,6 +154,10 @@ Geom make_geom(const das_plan_s* p) {
   g.t0fs = p->cfg.t0 * p->cfg.fs;
   g.apod = p->cfg.apod;
   g.fourF2 = (float)(4.0 * p->cfg.f_number * p->cfg.f_number);
+  g.iq = p->iq ? 1 : 0;
+  g.fcfs = p->iq ? p->fc / p->cfg.fs : 0.0;
+  const double ft = p->iq ? p->fc * p->cfg.t0 : 0.0;
+  g.fct0 = ft - std::floor(ft);
   return g;
 }
 
@@ -182,6 +189,7 @@ hipError_t launch_windowed(const das_plan_s* p, const Geom& g, int tile, const v
                            float* x, hipStream_t st) {
   const TileShape ts = tile_shape(tile);
   const Window w = make_window(p, ts);
+  if (p->iq) return tiled_forward_f32_iq(g, ts, w, ws, B, x, st);
   return launch_tiled_forward(g, p->cfg.storage, ts, w, ws, B, x, st);
 }
 
@@ -433,6 +441,14 @@ das_status das_plan_get_tile(das_plan p, int32_t* tile_index) {
   return DAS_OK;
 }
 
+das_status das_plan_set_iq(das_plan p, int32_t enable, double fc) {
+  if (das_status s = check_plan(p)) return s;
+  if (!std::isfinite(fc) || fc < 0.0) return fail(DAS_ERR_INVALID_ARG, "fc must be finite and >= 0");
+  p->iq = enable != 0;
+  p->fc = p->iq ? fc : 0.0;
+  return DAS_OK;
+}
+
 das_status das_plan_set_tile(das_plan p, int32_t tile_index) {
   if (das_status s = check_plan(p)) return s;
   if (tile_index < 0 || tile_index >= kNumTiles) return fail(DAS_ERR_INVALID_ARG, "bad tile index");
@@ -487,6 +503,11 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
   const Geom g = call_geom(p, ws, batch);
   const int algo = choose_algo(p, batch);
   hipError_t e = hipSuccess;
+  if (p->iq) {
+    if (batch % 2) return fail(DAS_ERR_INVALID_ARG, "complex baseband needs (I, Q) pairs: an even batch");
+    if (algo != DAS_ALGO_TILED || p->cfg.storage != DAS_STORE_F32)
+      return fail(DAS_ERR_UNSUPPORTED, "complex baseband runs in the windowed algorithm with f32 storage");
+  }
   if (algo == DAS_ALGO_PLAIN) {
     e = launch_plain_forward(g, static_cast<const float*>(ws), batch, x, st);
   } else if (algo == DAS_ALGO_TILED) {
@@ -505,6 +526,7 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
 
 das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, void* stream) {
   if (das_status s = check_plan(p)) return s;
+  if (p->iq) return fail(DAS_ERR_UNSUPPORTED, "the adjoint of the complex baseband form is not built");
   if (!gx || !gy) return fail(DAS_ERR_INVALID_ARG, "gx or gy is NULL");
   if (das_status s = check_batch(p, batch)) return s;
   DeviceGuard dg(p->device);
@@ -521,6 +543,7 @@ das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, vo
 das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int32_t batch,
                                 float* dLdc, void* stream) {
   if (das_status s = check_plan(p)) return s;
+  if (p->iq) return fail(DAS_ERR_UNSUPPORTED, "the gradient of the complex baseband form is not built");
   if (!y || !gx || !dLdc) return fail(DAS_ERR_INVALID_ARG, "y, gx or dLdc is NULL");
   if (das_status s = check_batch(p, batch)) return s;
   DeviceGuard dg(p->device);
@@ -568,6 +591,8 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
       return fail(DAS_ERR_INVALID_ARG, "all plans of a batched launch must be on one device");
     if (plans[i]->cfg.storage != plans[0]->cfg.storage)
       return fail(DAS_ERR_UNSUPPORTED, "all plans of a batched launch must share the storage type");
+    if (plans[i]->iq)
+      return fail(DAS_ERR_UNSUPPORTED, "complex baseband plans run through das_forward only");
   }
   const int algo0 = choose_algo(plans[0], batch[0]);
   for (int i = 0; i < count; ++i) {
@@ -623,6 +648,7 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
 das_status das_autotune(das_plan p, int32_t batch, void* stream) {
   if (das_status s = check_plan(p)) return s;
   if (das_status s = check_batch(p, batch)) return s;
+  if (p->iq && batch % 2) return fail(DAS_ERR_INVALID_ARG, "complex baseband needs an even batch");
   DeviceGuard dg(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int saved_algo = p->algo;

@@ -29,6 +29,9 @@ struct Geom {
   float fourF2;          // 4 F^2 (Hann f-number aperture test)
   const float* amax;     // FP8 workspaces: [batch] largest magnitude per item (fixes
                          // its scale), else nullptr
+  int iq;                // complex baseband mode: items (2b, 2b+1) are (I, Q)
+  double fcfs;           // IQ: carrier / sampling rate (revolutions per sample)
+  double fct0;           // IQ: frac(fc t0) (revolutions)
 };
 
 // Voxel tile handled by one workgroup of the windowed kernels.
@@ -131,6 +134,9 @@ hipError_t tiled_forward_bf16(const Geom& g, const TileShape& ts, const Window& 
                               int B, float* x, hipStream_t st);
 hipError_t tiled_forward_fp8(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
                              int B, float* x, hipStream_t st);
+// Complex baseband (IQ pairs), f32 storage.
+hipError_t tiled_forward_f32_iq(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
+                                int B, float* x, hipStream_t st);
 size_t tiled_lds_f32(const Geom& g, int bt, const Window& w);
 size_t tiled_lds_f16(const Geom& g, int bt, const Window& w);
 size_t tiled_lds_bf16(const Geom& g, int bt, const Window& w);

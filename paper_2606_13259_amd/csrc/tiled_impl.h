@@ -72,7 +72,8 @@ constexpr int chunk_elems() {
 
 struct QInfo {  // per transmit of the current group, 32 bytes
   float vx, vy, vz, vn, g;
-  int ktx, kind, pad;
+  int ktx, kind;
+  int rq;  // complex baseband: the transmit's phase term (float bits, revolutions)
 };
 
 // LDS layout (bytes), shared by the kernel and the host-side size query.
@@ -171,7 +172,7 @@ __device__ inline void stage_store(const Stage<BT, QN, MC>& st, float* win, int 
 
 // One tile (tile index `tile`, batch items b0 .. b0+BT-1) of the windowed
 // forward; all 256 threads of the workgroup call it together.
-template <class T, int BT, int QN, bool WTX>
+template <class T, int BT, int QN, bool WTX, bool IQ = false>
 __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Window& win,
                                  const T* __restrict__ ws, int B, float* __restrict__ x, int ntx,
                                  int nty, int ntiles, int tile, int b0, unsigned char* smem,
@@ -328,18 +329,28 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
       __syncthreads();
       if (t < qn) {
         const TxRef r = make_tx_ref(g, txl ? txl[q0 + t] : q0 + t, px, py, pz);
-        qinfo[t] = QInfo{r.vx, r.vy, r.vz, r.vn, r.g, r.ktx, r.kind, 0};
+        // complex baseband: the transmit's phase term frac(fc/fs ktx + fc t0)
+        // in revolutions (FP64 before rounding: ktx reaches thousands)
+        int rq_bits = 0;
+        if constexpr (IQ) {
+          const double rv = g.fcfs * (double)r.ktx + g.fct0;
+          rq_bits = __float_as_int((float)(rv - floor(rv)));
+        }
+        qinfo[t] = QInfo{r.vx, r.vy, r.vz, r.vn, r.g, r.ktx, r.kind, rq_bits};
         ktx_s[t] = r.ktx;
       }
       __syncthreads();
       float bq[QN];
       float wq[WTX ? QN : 1];
+      float rq[IQ ? QN : 1];
 #pragma unroll
       for (int q = 0; q < QN; ++q) {
         bq[q] = 0.f;
         if (WTX) wq[WTX ? q : 0] = 0.f;
+        if (IQ) rq[IQ ? q : 0] = 0.f;
         if (q < qn) {
           const QInfo qi = qinfo[q];
+          if (IQ) rq[IQ ? q : 0] = __int_as_float(qi.rq);
           TxRef r;
           r.vx = qi.vx; r.vy = qi.vy; r.vz = qi.vz; r.vn = qi.vn; r.kind = qi.kind;
           bq[q] = fmaf(delta_tx(r, dx, dy, dz, dp2), fscf, qi.g);
@@ -373,6 +384,12 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           const float w = rx_weight(g, mm & 0xffff, ax, ay, az);
           const float en = __builtin_amdgcn_sqrtf(ex * ex + ey * ey + ez * ez);
           const float a = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, eh);
+          // complex baseband: the element's phase term frac(fc/fs krx)
+          float rm = 0.f;
+          if constexpr (IQ) {
+            const double rv = g.fcfs * (double)__builtin_amdgcn_readfirstlane(eK[e]);
+            rm = (float)(rv - floor(rv));
+          }
           constexpr int QP = Row<QN>::QP;
           // tap index i = floor(f) + dint is in [1, 2 dint + 1] (window bound)
           const float* base = wsm + (mc * WS + win.dint) * QP * BT;
@@ -382,10 +399,11 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
             // with transmit weights the group may be short (sparse list): stop
             // at its last transmit (block-uniform)
             if (WTX && qa >= qn) break;
-            float s1[QR][BT], s2[QR][BT], al[QR];
+            float s1[QR][BT], s2[QR][BT], al[QR], fr[IQ ? QR : 1];
 #pragma unroll
             for (int r = 0; r < QR; ++r) {
               const float f = a + bq[qa + r];
+              if (IQ) fr[IQ ? r : 0] = f;
               al[r] = frac_f32(f);
               const float* pp = base + (__mul24(floor_i32(f), QP * BT) + (qa + r) * BT);
 #pragma unroll
@@ -398,9 +416,24 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
 #pragma unroll
             for (int r = 0; r < QR; ++r) {
               const float wt = WTX ? w * wq[WTX ? qa + r : 0] : w;
+              if constexpr (IQ) {
+                // remodulate by exp(i 2 pi fc tau): revolutions fc/fs (ktx + krx
+                // + f) + fc t0, reduced to [0, 1) before the hardware sine and
+                // cosine (which take revolutions)
+                const float rev = frac_f32(rq[qa + r] + rm + (float)g.fcfs * fr[r]);
+                const float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
 #pragma unroll
-              for (int b = 0; b < BT; ++b)
-                acc[b] = fmaf(wt, fmaf(al[r], s2[r][b], fmaf(-al[r], s1[r][b], s1[r][b])), acc[b]);
+                for (int b = 0; b < BT; b += 2) {
+                  const float vi = fmaf(al[r], s2[r][b], fmaf(-al[r], s1[r][b], s1[r][b]));
+                  const float vq = fmaf(al[r], s2[r][b + 1], fmaf(-al[r], s1[r][b + 1], s1[r][b + 1]));
+                  acc[b] = fmaf(wt, fmaf(cs, vi, -sn * vq), acc[b]);
+                  acc[b + 1] = fmaf(wt, fmaf(sn, vi, cs * vq), acc[b + 1]);
+                }
+              } else {
+#pragma unroll
+                for (int b = 0; b < BT; ++b)
+                  acc[b] = fmaf(wt, fmaf(al[r], s2[r][b], fmaf(-al[r], s1[r][b], s1[r][b])), acc[b]);
+              }
             }
           }
         }
@@ -436,6 +469,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ti
   const int tile = bx >= (int)gridDim.x / per * per ? bx : bx / per * per + (bx % per % X) * C + (bx % per) / X;
   tile_body<T, BT, QN, WTX>(g, ts, win, ws, B, x, ntx, nty, ntiles, tile, blockIdx.y * BT, smem,
                             ktx_s, txl_s);
+}
+
+// Complex baseband (IQ) variant: batch items (2b, 2b+1) are the I and Q
+// records of one complex item; every term is remodulated by exp(i 2 pi fc tau)
+// (the same tile schedule and windows as tiled_forward).
+template <class T, int BT, int QN, bool WTX>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void tiled_forward_iq(
+    Geom g, TileShape ts, Window win, const T* __restrict__ ws, int B, float* __restrict__ x,
+    int ntx, int nty, int ntiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int ktx_s[16];
+  __shared__ int txl_s[72];
+  constexpr int X = 8, C = 16, per = X * C;
+  const int bx = (int)blockIdx.x;
+  const int tile = bx >= (int)gridDim.x / per * per ? bx : bx / per * per + (bx % per % X) * C + (bx % per) / X;
+  tile_body<T, BT, QN, WTX, true>(g, ts, win, ws, B, x, ntx, nty, ntiles, tile, blockIdx.y * BT, smem,
+                                  ktx_s, txl_s);
 }
 
 // Several forward passes in one persistent launch: in round r, workgroup w
@@ -494,6 +544,47 @@ hipError_t launch_t(const Geom& g, const TileShape& ts, const Window& w, const v
 
 // Transmit-group size for Q transmits.
 inline int group_size(int Q) { return Q == 1 ? 1 : Q <= 4 ? 4 : Q <= 8 ? 8 : 16; }
+
+template <class T, int BT, int QN, bool WTX>
+hipError_t launch_iq_t(const Geom& g, const TileShape& ts, const Window& w, const void* ws, int B,
+                       float* x, hipStream_t st) {
+  const int ntx = (g.n[0] + ts.tx - 1) / ts.tx, nty = (g.n[1] + ts.ty - 1) / ts.ty,
+            ntz = (g.n[2] + ts.tz - 1) / ts.tz;
+  const int ntiles = ntx * nty * ntz;
+  const size_t lds = lds_bytes_t<BT, QN>(w);
+  dim3 grid(ntiles, (B + BT - 1) / BT);
+  auto kern = tiled_forward_iq<T, BT, QN, WTX>;
+  if (lds > 65536) {
+    hipError_t e =
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, g, ts, w, static_cast<const T*>(ws), B, x, ntx,
+                     nty, ntiles);
+  return hipGetLastError();
+}
+
+// Complex baseband launch: B even (I, Q pairs), two or four items per thread.
+template <class T>
+hipError_t launch_iq(const Geom& g, const TileShape& ts, const Window& w, const void* ws, int B,
+                     float* x, hipStream_t st) {
+  const bool wtx = g.w_tx != nullptr;
+  auto pick = [&](auto bt_tag) -> hipError_t {
+    constexpr int BT = decltype(bt_tag)::value;
+    switch (group_size(g.Q)) {
+      case 1: return wtx ? launch_iq_t<T, BT, 1, true>(g, ts, w, ws, B, x, st)
+                         : launch_iq_t<T, BT, 1, false>(g, ts, w, ws, B, x, st);
+      case 4: return wtx ? launch_iq_t<T, BT, 4, true>(g, ts, w, ws, B, x, st)
+                         : launch_iq_t<T, BT, 4, false>(g, ts, w, ws, B, x, st);
+      case 8: return wtx ? launch_iq_t<T, BT, 8, true>(g, ts, w, ws, B, x, st)
+                         : launch_iq_t<T, BT, 8, false>(g, ts, w, ws, B, x, st);
+      default: return wtx ? launch_iq_t<T, BT, 16, true>(g, ts, w, ws, B, x, st)
+                          : launch_iq_t<T, BT, 16, false>(g, ts, w, ws, B, x, st);
+    }
+  };
+  if (B >= 4) return pick(std::integral_constant<int, 4>());
+  return pick(std::integral_constant<int, 2>());
+}
 
 template <class T, int BT>
 hipError_t launch_bt(const Geom& g, const TileShape& ts, const Window& w, const void* ws, int B,

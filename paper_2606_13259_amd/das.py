@@ -99,6 +99,7 @@ def lib():
             "das_plan_set_tile": [_P, _I],
             "das_tile_shape": [_I, ctypes.POINTER(_I)],
             "das_debug_delays": [_P, _I, _I, _I, _I, _I, _P, _P],
+            "das_plan_set_iq": [_P, _I, ctypes.c_double],
             "das_clutter_workspace_bytes": [_I, ctypes.POINTER(ctypes.c_size_t)],
             "das_clutter_filter": [_P, _I, ctypes.c_int64, _I, _I, _P, _P, _P, _P, _P],
         }
@@ -304,6 +305,11 @@ class Plan:
             assert w_tx.dtype == torch.float32 and w_tx.is_contiguous() and w_tx.numel() == self.Q * self.N
         self._w_tx = w_tx
         _check(lib().das_plan_set_tx_weights(self.handle, _ptr(w_tx)), "das_plan_set_tx_weights")
+
+    def set_iq(self, fc: float, enable: bool = True):
+        """Complex baseband mode: batch items are (I, Q) pairs demodulated at
+        fc (Hz); the forward remodulates every term by exp(i 2 pi fc tau)."""
+        _check(lib().das_plan_set_iq(self.handle, int(bool(enable)), float(fc)), "das_plan_set_iq")
 
     def set_algo(self, algo: str):
         _check(lib().das_plan_set_algo(self.handle, ALGO[algo]), "das_plan_set_algo")
