@@ -170,9 +170,81 @@ __device__ inline void stage_store(const Stage<BT, QN, MC>& st, float* win, int 
   }
 }
 
+// Single-item workspaces (B = 1, the headline case) stage windows four
+// samples per lane: samples of a window are contiguous in ws[Q][M][K], so 16
+// lanes cover a 64-sample window with one load of four samples each (16, 8 or
+// 4 bytes), a wavefront four windows per instruction (a quarter of the
+// address work of one sample per lane).  The LDS layout stays [mc][sample][q] (the taps of all transmits of
+// a lane one immediate offset apart); the four samples go out as four
+// stores.
+// The layout must be [Q][M][K] (a plan of one item): a persistent launch can
+// run its one-item-per-thread body over plans of several items, so the
+// choice is made at run time on the plan's batch (the staging registers are
+// shared: Stage<1, QN, MC> holds 16 floats, four rounds of four samples).
+template <class T, int BT>
+constexpr bool kVecStage = BT == 1;
+
+template <class T, int QN, int MC>
+__device__ inline void stage_load4(Stage<1, QN, MC>& st, const T* __restrict__ ws, const int* ktx,
+                                   const int* ek, const int* em, const int* txl, int c0, int q0,
+                                   int qn, int mcn, int M, int K, int W, int dint, int wave,
+                                   int lane) {
+  const int s = 4 * (lane & 15);  // first sample of this lane within its window
+  static_assert(Stage<1, QN, MC>::WPW == 16, "64 windows per chunk");
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int wi = 16 * k + 4 * wave + (lane >> 4);
+    const int q = wi / MC, mc = wi % MC;
+    float4 v = {0.f, 0.f, 0.f, 0.f};
+    if (q < qn && mc < mcn && s < W) {
+      const int e = c0 + mc;
+      const int m = em[e] & 0xffff;
+      const int j = ktx[q] + ek[e] - dint + s;
+      const int qt = txl ? txl[q0 + q] : q0 + q;
+      const T* chan = ws + ((size_t)qt * M + m) * (size_t)K;
+      if (j >= 0 && j + 3 < K) {
+        T u[4];
+        __builtin_memcpy(u, chan + j, sizeof(u));
+        v = float4{to_f32<T>(u[0]), to_f32<T>(u[1]), to_f32<T>(u[2]), to_f32<T>(u[3])};
+      } else {
+        v.x = (j >= 0 && j < K) ? to_f32<T>(chan[j]) : 0.f;
+        v.y = (j + 1 >= 0 && j + 1 < K) ? to_f32<T>(chan[j + 1]) : 0.f;
+        v.z = (j + 2 >= 0 && j + 2 < K) ? to_f32<T>(chan[j + 2]) : 0.f;
+        v.w = (j + 3 >= 0 && j + 3 < K) ? to_f32<T>(chan[j + 3]) : 0.f;
+      }
+    }
+    st.v[4 * k + 0][0] = v.x;
+    st.v[4 * k + 1][0] = v.y;
+    st.v[4 * k + 2][0] = v.z;
+    st.v[4 * k + 3][0] = v.w;
+  }
+}
+
+template <int QN, int MC>
+__device__ inline void stage_store4(const Stage<1, QN, MC>& st, float* win, int mcn, int W,
+                                    int wave, int lane) {
+  const int s = 4 * (lane & 15);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int wi = 16 * k + 4 * wave + (lane >> 4);
+    const int q = wi / MC, mc = wi % MC;
+    constexpr int QP = Row<QN>::QP;
+    if (mc < mcn && s < W) {
+      float* dst = win + (mc * WS + s) * QP + q;
+      dst[0] = st.v[4 * k][0];
+      if (s + 1 < W) dst[QP] = st.v[4 * k + 1][0];
+      if (s + 2 < W) dst[2 * QP] = st.v[4 * k + 2][0];
+      if (s + 3 < W) dst[3 * QP] = st.v[4 * k + 3][0];
+    }
+  }
+}
+
 // One tile (tile index `tile`, batch items b0 .. b0+BT-1) of the windowed
 // forward; all 256 threads of the workgroup call it together.
-template <class T, int BT, int QN, bool WTX, bool IQ = false>
+// RUNTIME_VEC: the one-item staging path is chosen per plan at run time (the
+// persistent kernel, whose one-item-per-thread body may serve plans of
+// several items); otherwise BT == 1 implies a one-item plan.
+template <class T, int BT, int QN, bool WTX, bool IQ = false, bool RUNTIME_VEC = false>
 __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Window& win,
                                  const T* __restrict__ ws, int B, float* __restrict__ x, int ntx,
                                  int nty, int ntiles, int tile, int b0, unsigned char* smem,
@@ -359,18 +431,46 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
         }
       }
 
+      const bool vec = kVecStage<T, BT> && (!RUNTIME_VEC || B == 1);  // uniform
       Stage<BT, QN, MC> st;
-      if (nact > 0)
-        stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, txl, 0, q0, qn, min(MC, nact), M, K, B,
-                                  b0, W, win.dint, wave, lane);
+      if (nact > 0) {
+        if constexpr (kVecStage<T, BT>) {
+          if (vec)
+            stage_load4<T, QN, MC>(st, ws, ktx_s, eK, eM, txl, 0, q0, qn, min(MC, nact), M, K, W,
+                                   win.dint, wave, lane);
+          else
+            stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, txl, 0, q0, qn, min(MC, nact), M, K,
+                                      B, b0, W, win.dint, wave, lane);
+        } else {
+          stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, txl, 0, q0, qn, min(MC, nact), M, K, B,
+                                    b0, W, win.dint, wave, lane);
+        }
+      }
       for (int c0 = 0; c0 < nact; c0 += MC) {
         const int mcn = min(MC, nact - c0);
         __syncthreads();  // the previous chunk is no longer read
-        stage_store<BT, QN, MC>(st, wsm, mcn, W, wave, lane);
+        if constexpr (kVecStage<T, BT>) {
+          if (vec)
+            stage_store4<QN, MC>(st, wsm, mcn, W, wave, lane);
+          else
+            stage_store<BT, QN, MC>(st, wsm, mcn, W, wave, lane);
+        } else {
+          stage_store<BT, QN, MC>(st, wsm, mcn, W, wave, lane);
+        }
         __syncthreads();
-        if (c0 + MC < nact)
-          stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, txl, c0 + MC, q0, qn,
-                                    min(MC, nact - c0 - MC), M, K, B, b0, W, win.dint, wave, lane);
+        if (c0 + MC < nact) {
+          bool done = false;
+          if constexpr (kVecStage<T, BT>) {
+            if (vec) {
+              stage_load4<T, QN, MC>(st, ws, ktx_s, eK, eM, txl, c0 + MC, q0, qn,
+                                     min(MC, nact - c0 - MC), M, K, W, win.dint, wave, lane);
+              done = true;
+            }
+          }
+          if (!done)
+            stage_load<T, BT, QN, MC>(st, ws, ktx_s, eK, eM, txl, c0 + MC, q0, qn,
+                                      min(MC, nact - c0 - MC), M, K, B, b0, W, win.dint, wave, lane);
+        }
         // ---- interpolate and accumulate ----
         for (int mc = 0; mc < mcn; ++mc) {
           const int e = c0 + mc;
@@ -513,7 +613,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void ti
     const int local = item - a.first[p];
     const int tile = local % w.ntiles, bg = local / w.ntiles;
     __syncthreads();  // the previous item no longer reads LDS
-    tile_body<T, BT, QN, WTX>(w.g, w.ts, w.win, static_cast<const T*>(w.ws), w.B, w.x, w.ntx,
+    tile_body<T, BT, QN, WTX, false, true>(w.g, w.ts, w.win, static_cast<const T*>(w.ws), w.B, w.x, w.ntx,
                               w.nty, w.ntiles, tile, bg * BT, smem, ktx_s, txl_s);
   }
 }
