@@ -174,9 +174,12 @@ __device__ inline void stage_store(const Stage<BT, QN, MC>& st, float* win, int 
 // samples per lane: samples of a window are contiguous in ws[Q][M][K], so 16
 // lanes cover a 64-sample window with one load of four samples each (16, 8 or
 // 4 bytes), a wavefront four windows per instruction (a quarter of the
-// address work of one sample per lane).  The LDS layout stays [mc][sample][q] (the taps of all transmits of
-// a lane one immediate offset apart); the four samples go out as four
-// stores.
+// address work of one sample per lane).  The LDS layout stays
+// [mc][sample][q] (the taps of all transmits of a lane one immediate offset
+// apart); the four samples go out as four stores.  The four window groups of an instruction take consecutive
+// transmits of one element (q = wi mod QN), so their stores land one bank
+// apart; taking consecutive elements instead puts all four groups on the
+// same banks (an element is WS * QP words, a multiple of the bank count).
 // The layout must be [Q][M][K] (a plan of one item): a persistent launch can
 // run its one-item-per-thread body over plans of several items, so the
 // choice is made at run time on the plan's batch (the staging registers are
@@ -184,17 +187,24 @@ __device__ inline void stage_store(const Stage<BT, QN, MC>& st, float* win, int 
 template <class T, int BT>
 constexpr bool kVecStage = BT == 1;
 
+// Lane -> (window group g, first sample s): lanes 8g .. 8g+7 take samples
+// 0 .. 31 of window g and lanes 32+8g .. 32+8g+7 samples 32 .. 63, so each
+// half-wavefront (the LDS serves 32 lanes a cycle) stores 4 windows x 8
+// quads, banks 4j + g: all 32 distinct.
+__device__ inline int vec_group(int lane) { return (lane >> 3) & 3; }
+__device__ inline int vec_sample(int lane) { return 4 * ((lane & 7) | ((lane >> 5) << 3)); }
+
 template <class T, int QN, int MC>
 __device__ inline void stage_load4(Stage<1, QN, MC>& st, const T* __restrict__ ws, const int* ktx,
                                    const int* ek, const int* em, const int* txl, int c0, int q0,
                                    int qn, int mcn, int M, int K, int W, int dint, int wave,
                                    int lane) {
-  const int s = 4 * (lane & 15);  // first sample of this lane within its window
+  const int s = vec_sample(lane);  // first sample of this lane within its window
   static_assert(Stage<1, QN, MC>::WPW == 16, "64 windows per chunk");
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int wi = 16 * k + 4 * wave + (lane >> 4);
-    const int q = wi / MC, mc = wi % MC;
+    const int wi = 16 * k + 4 * wave + vec_group(lane);
+    const int q = wi % QN, mc = wi / QN;
     float4 v = {0.f, 0.f, 0.f, 0.f};
     if (q < qn && mc < mcn && s < W) {
       const int e = c0 + mc;
@@ -223,11 +233,11 @@ __device__ inline void stage_load4(Stage<1, QN, MC>& st, const T* __restrict__ w
 template <int QN, int MC>
 __device__ inline void stage_store4(const Stage<1, QN, MC>& st, float* win, int mcn, int W,
                                     int wave, int lane) {
-  const int s = 4 * (lane & 15);
+  const int s = vec_sample(lane);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int wi = 16 * k + 4 * wave + (lane >> 4);
-    const int q = wi / MC, mc = wi % MC;
+    const int wi = 16 * k + 4 * wave + vec_group(lane);
+    const int q = wi % QN, mc = wi / QN;
     constexpr int QP = Row<QN>::QP;
     if (mc < mcn && s < W) {
       float* dst = win + (mc * WS + s) * QP + q;
