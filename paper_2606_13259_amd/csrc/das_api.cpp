@@ -51,6 +51,24 @@ TileShape tile_shape(int idx) {
   t.tz = kTiles[idx][2];
   t.lx = ilog2(t.tx);
   t.lxy = ilog2(t.tx * t.ty);
+  // wavefront box: halve the longest side (z, then x, then y on ties) until
+  // 64 voxels remain
+  int w[3] = {t.tx, t.ty, t.tz};
+  while (w[0] * w[1] * w[2] > 64) {
+    int d = 2;
+    if (w[0] > w[d]) d = 0;
+    if (w[1] > w[d]) d = 1;
+    w[d] /= 2;
+  }
+  t.wx = w[0];
+  t.wy = w[1];
+  t.wz = w[2];
+  t.wlx = ilog2(t.wx);
+  t.wlxy = ilog2(t.wx * t.wy);
+  t.bx = t.tx / t.wx;
+  t.by = t.ty / t.wy;
+  t.blx = ilog2(t.bx);
+  t.blxy = ilog2(t.bx * t.by);
   return t;
 }
 

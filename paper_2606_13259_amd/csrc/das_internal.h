@@ -38,6 +38,13 @@ struct Geom {
 struct TileShape {
   int tx, ty, tz;        // voxels per tile along x, y, z (tx*ty*tz == 256)
   int lx, lxy;           // log2(tx), log2(tx*ty)
+  // The windowed forward splits a tile into four wavefront boxes of 64
+  // voxels, as near to cubes as the tile allows (the smallest bounding
+  // spheres for the per-wavefront element test):
+  int wx, wy, wz;        // voxels per wavefront box along x, y, z
+  int wlx, wlxy;         // log2(wx), log2(wx*wy)
+  int bx, by;            // wavefront boxes along x, y (bx*by*bz == 4)
+  int blx, blxy;         // log2(bx), log2(bx*by)
 };
 
 // Window geometry of the windowed kernels for one launch (depends on c).

@@ -276,7 +276,11 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
   const int wave = t >> 6, lane = t & 63;
   const int ntz = ntiles / (ntx * nty);
   const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = ntz - 1 - tile / (ntx * nty);
-  const int lx = t & (ts.tx - 1), ly = (t >> ts.lx) & (ts.ty - 1), lz = t >> ts.lxy;
+  // wavefront `wave` covers box (bx, by, bz) of the tile, x fastest inside
+  const int bxi = wave & (ts.bx - 1), byi = (wave >> ts.blx) & (ts.by - 1), bzi = wave >> ts.blxy;
+  const int lx = bxi * ts.wx + (lane & (ts.wx - 1));
+  const int ly = byi * ts.wy + ((lane >> ts.wlx) & (ts.wy - 1));
+  const int lz = bzi * ts.wz + (lane >> ts.wlxy);
   const int ix = tix * ts.tx + lx, iy = tiy * ts.ty + ly, iz = tiz * ts.tz + lz;
   const int K = g.K, M = g.M;
   const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
@@ -294,16 +298,16 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
   const uint32_t mybit = 1u << (16 + wave);
 
   // Bounding spheres (relative to the tile reference) of the tile and of the
-  // four wavefront boxes (64 consecutive lanes form a box of the tile).
+  // four wavefront boxes.
   const float Rt = sqrtf(hx * hx * sx * sx + hy * hy * sy * sy + hz * hz * sz * sz);
   float wcx[4], wcy[4], wcz[4], wr[4];
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    const int a = 64 * w, bb = 64 * w + 63;
-    const float ax0 = (float)(a & (ts.tx - 1)), ay0 = (float)((a >> ts.lx) & (ts.ty - 1)),
-                az0 = (float)(a >> ts.lxy);
-    const float ax1 = (float)(bb & (ts.tx - 1)), ay1 = (float)((bb >> ts.lx) & (ts.ty - 1)),
-                az1 = (float)(bb >> ts.lxy);
+    const float ax0 = (float)((w & (ts.bx - 1)) * ts.wx);
+    const float ay0 = (float)(((w >> ts.blx) & (ts.by - 1)) * ts.wy);
+    const float az0 = (float)((w >> ts.blxy) * ts.wz);
+    const float ax1 = ax0 + (float)(ts.wx - 1), ay1 = ay0 + (float)(ts.wy - 1),
+                az1 = az0 + (float)(ts.wz - 1);
     wcx[w] = (0.5f * (ax0 + ax1) - hx) * sx;
     wcy[w] = (0.5f * (ay0 + ay1) - hy) * sy;
     wcz[w] = (0.5f * (az0 + az1) - hz) * sz;
