@@ -508,14 +508,13 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           // tap index i = floor(f) + dint is in [1, 2 dint + 1] (window bound)
           const float* base = wsm + (mc * WS + win.dint) * QP * BT;
           constexpr int QR = QN * BT <= 8 ? QN : (8 / BT < 1 ? 1 : 8 / BT);
+          // one group of QG transmits starting at qa: all tap reads first,
+          // then the interpolation and accumulation
+          auto taps = [&](auto qg_tag, int qa) {
+            constexpr int QG = decltype(qg_tag)::value;
+            float s1[QG][BT], s2[QG][BT], al[QG], fr[IQ ? QG : 1];
 #pragma unroll
-          for (int qa = 0; qa < QN; qa += QR) {
-            // with transmit weights the group may be short (sparse list): stop
-            // at its last transmit (block-uniform)
-            if (WTX && qa >= qn) break;
-            float s1[QR][BT], s2[QR][BT], al[QR], fr[IQ ? QR : 1];
-#pragma unroll
-            for (int r = 0; r < QR; ++r) {
+            for (int r = 0; r < QG; ++r) {
               const float f = a + bq[qa + r];
               if (IQ) fr[IQ ? r : 0] = f;
               al[r] = frac_f32(f);
@@ -528,7 +527,7 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
             }
             __builtin_amdgcn_sched_barrier(0);  // all reads of the group issue first
 #pragma unroll
-            for (int r = 0; r < QR; ++r) {
+            for (int r = 0; r < QG; ++r) {
               const float wt = WTX ? w * wq[WTX ? qa + r : 0] : w;
               if constexpr (IQ) {
                 // remodulate by exp(i 2 pi fc tau): revolutions fc/fs (ktx + krx
@@ -548,6 +547,21 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
                 for (int b = 0; b < BT; ++b)
                   acc[b] = fmaf(wt, fmaf(al[r], s2[r][b], fmaf(-al[r], s1[r][b], s1[r][b])), acc[b]);
               }
+            }
+          };
+          // with transmit weights the group may be short (sparse list): stop
+          // at its last transmit (block-uniform); a list of at most four
+          // transmits (the common case of selective weights) takes one
+          // four-transmit group instead of a full one
+          bool short_list = false;
+          if constexpr (WTX && QR > 4) short_list = qn <= 4;
+          if (short_list) {
+            if constexpr (WTX && QR > 4) taps(std::integral_constant<int, 4>(), 0);
+          } else {
+#pragma unroll
+            for (int qa = 0; qa < QN; qa += QR) {
+              if (WTX && qa >= qn) break;
+              taps(std::integral_constant<int, QR>(), qa);
             }
           }
         }
