@@ -507,7 +507,11 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           constexpr int QP = Row<QN>::QP;
           // tap index i = floor(f) + dint is in [1, 2 dint + 1] (window bound)
           const float* base = wsm + (mc * WS + win.dint) * QP * BT;
-          constexpr int QR = QN * BT <= 8 ? QN : (8 / BT < 1 ? 1 : 8 / BT);
+          // transmits per unit of the tap loop: eight one-item taps, or four
+          // with transmit weights, whose sparse lists are short (the loop
+          // stops after the unit holding the list's last transmit)
+          constexpr int QR0 = QN * BT <= 8 ? QN : (8 / BT < 1 ? 1 : 8 / BT);
+          constexpr int QR = WTX && QR0 > 4 ? 4 : QR0;
           // one group of QG transmits starting at qa: all tap reads first,
           // then the interpolation and accumulation
           auto taps = [&](auto qg_tag, int qa) {
@@ -553,16 +557,10 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           // at its last transmit (block-uniform); a list of at most four
           // transmits (the common case of selective weights) takes one
           // four-transmit group instead of a full one
-          bool short_list = false;
-          if constexpr (WTX && QR > 4) short_list = qn <= 4;
-          if (short_list) {
-            if constexpr (WTX && QR > 4) taps(std::integral_constant<int, 4>(), 0);
-          } else {
 #pragma unroll
-            for (int qa = 0; qa < QN; qa += QR) {
-              if (WTX && qa >= qn) break;
-              taps(std::integral_constant<int, QR>(), qa);
-            }
+          for (int qa = 0; qa < QN; qa += QR) {
+            if (WTX && qa >= qn) break;  // block-uniform
+            taps(std::integral_constant<int, QR>(), qa);
           }
         }
       }
