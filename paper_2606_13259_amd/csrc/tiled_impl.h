@@ -211,7 +211,8 @@ __device__ inline void stage_load4(Stage<1, QN, MC>& st, const T* __restrict__ w
       const int m = em[e] & 0xffff;
       const int j = ktx[q] + ek[e] - dint + s;
       const int qt = txl ? txl[q0 + q] : q0 + q;
-      const T* chan = ws + ((size_t)qt * M + m) * (size_t)K;
+      // qt M + m < 2^28 (Q <= 4096, M <= 65535): one 32 x 32 -> 64-bit product
+      const T* chan = ws + (size_t)(unsigned)(qt * M + m) * (unsigned)K;
       if (j >= 0 && j + 3 < K) {
         T u[4];
         __builtin_memcpy(u, chan + j, sizeof(u));
