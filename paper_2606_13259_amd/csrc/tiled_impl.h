@@ -78,7 +78,7 @@ struct QInfo {  // per transmit of the current group, 32 bytes
 
 // LDS layout (bytes), shared by the kernel and the host-side size query.
 struct Layout {
-  int win, ex, ey, ez, eh, ek, em, q, wc, total;
+  int win, ex, ey, ez, eh, en, ek, em, q, wc, total;
 };
 __host__ __device__ inline Layout layout(int QN, int MC, int BT, int W) {
   Layout L;
@@ -89,6 +89,7 @@ __host__ __device__ inline Layout layout(int QN, int MC, int BT, int W) {
   L.ey = o; o += EMAX * 4;
   L.ez = o; o += EMAX * 4;
   L.eh = o; o += EMAX * 4;
+  L.en = o; o += EMAX * 4;
   L.ek = o; o += EMAX * 4;
   L.em = o; o += EMAX * 4;
   L.q = o; o += 16 * (int)sizeof(QInfo);
@@ -268,6 +269,7 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
   float* eY = reinterpret_cast<float*>(smem + L.ey);
   float* eZ = reinterpret_cast<float*>(smem + L.ez);
   float* eH = reinterpret_cast<float*>(smem + L.eh);
+  float* eN = reinterpret_cast<float*>(smem + L.en);
   int* eK = reinterpret_cast<int*>(smem + L.ek);
   int* eM = reinterpret_cast<int*>(smem + L.em);
   QInfo* qinfo = reinterpret_cast<QInfo*>(smem + L.q);
@@ -399,10 +401,12 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
         const double R = sqrt(ex * ex + ey * ey + ez * ez);
         const double fr = R * g.fsc;
         const double fl = floor(fr);
-        eX[e] = (float)ex;
-        eY[e] = (float)ey;
-        eZ[e] = (float)ez;
+        const float fx = (float)ex, fy = (float)ey, fz = (float)ez;
+        eX[e] = fx;
+        eY[e] = fy;
+        eZ[e] = fz;
         eH[e] = (float)(fr - fl);
+        eN[e] = __builtin_amdgcn_sqrtf(fx * fx + fy * fy + fz * fz);  // |r_m - p_tile|, FP32
         eK[e] = (int)fl;
         eM[e] = (int)(m | (mask << 16));
       }
@@ -497,7 +501,7 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           const float eh = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(eH[e])));
           const float ax = ex + dx, ay = ey + dy, az = ez + dz;
           const float w = rx_weight(g, mm & 0xffff, ax, ay, az);
-          const float en = __builtin_amdgcn_sqrtf(ex * ex + ey * ey + ez * ez);
+          const float en = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(eN[e])));
           const float a = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, eh);
           // complex baseband: the element's phase term frac(fc/fs krx)
           float rm = 0.f;
