@@ -112,11 +112,8 @@ __device__ inline float delta_tx(const TxRef& t, float dx, float dy, float dz, f
 // w = (1 + cos(pi rho / a)) / 2 = cos^2(pi rho / (2a)) inside the cone.
 // cos(pi sqrt(t) / 2) for t = rho^2/a^2 in [0, 1) is evaluated as its Taylor
 // series in t (entire in t, no square root), 8 terms: error < 1e-10.
-__device__ inline float hann_fnum(float dx, float dy, float dz, float nx, float ny, float nz,
-                                  float fourF2) {
-  const float z = dx * nx + dy * ny + dz * nz;
-  const float lx = dx - z * nx, ly = dy - z * ny, lz = dz - z * nz;
-  const float rho2 = lx * lx + ly * ly + lz * lz;
+// The weight from the axial distance z and the squared lateral distance rho2.
+__device__ inline float hann_weight(float z, float rho2, float fourF2) {
   const float zz = z * z;
   const float t4 = rho2 * fourF2;
   if (!(z > 0.f) || !(t4 < zz)) return 0.f;
@@ -133,15 +130,19 @@ __device__ inline float hann_fnum(float dx, float dy, float dz, float nx, float 
   return c * c;
 }
 
+__device__ inline float hann_fnum(float dx, float dy, float dz, float nx, float ny, float nz,
+                                  float fourF2) {
+  const float z = dx * nx + dy * ny + dz * nz;
+  const float lx = dx - z * nx, ly = dy - z * ny, lz = dz - z * nz;
+  return hann_weight(z, lx * lx + ly * ly + lz * lz, fourF2);
+}
+
 __device__ inline float rx_weight(const Geom& g, int m, float dx, float dy, float dz) {
   if (g.apod != DAS_APOD_HANN_FNUM) return 1.f;
-  float nx = 0.f, ny = 0.f, nz = 1.f;
-  if (g.enorm) {
-    nx = g.enorm[3 * m + 0];
-    ny = g.enorm[3 * m + 1];
-    nz = g.enorm[3 * m + 2];
-  }
-  return hann_fnum(dx, dy, dz, nx, ny, nz, g.fourF2);
+  // default normals (+z): z = dz and rho^2 = dx^2 + dy^2 directly
+  if (!g.enorm) return hann_weight(dz, dx * dx + dy * dy, g.fourF2);
+  return hann_fnum(dx, dy, dz, g.enorm[3 * m + 0], g.enorm[3 * m + 1], g.enorm[3 * m + 2],
+                   g.fourF2);
 }
 
 // Is any point of the sphere (centre c, radius R) inside the receive cone of
