@@ -77,6 +77,26 @@ def test_cfg2_subblocks(gpu, cfg2_blocks, storage, algo):
             check_close(x, xr, REL_L2_F32, ABS_F32, f"  vs oracle on {storage}-rounded data")
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "fp8"])
+def test_one_item_staging_short_odd_record(gpu, storage):
+    """One-item windows are staged four samples per lane; with K = 41 (odd,
+    shorter than a window) and t0 = 13.5 us, 12 % of the taps fall before the
+    record and 11 % after it, so staging takes its per-sample path at both
+    ends and its four-sample loads start at every alignment."""
+    das = _das()
+    g = synth.cfg2(dims=(11, 9, 13), n_side=8).replace(num_samples=41, t0=13.5e-6)
+    y = synth.random_channel_data(g, 1, seed=41)
+    plan = das.Plan(g, max_batch=1, storage=storage, algo="tiled")
+    x = plan.forward(y.to(gpu)).cpu().numpy()[0]
+    xo = oracle.forward(y.numpy(), g)[0]
+    if storage == "f32":
+        check_close(x, xo, REL_L2_F32, ABS_F32, "K=41 f32")
+    else:
+        check_close(x, xo, *lowp_bars(storage), f"K=41 {storage}")
+        xr = oracle.forward(round_like_storage(y.numpy(), storage), g)[0]
+        check_close(x, xr, REL_L2_F32, ABS_F32, f"  vs oracle on {storage}-rounded data")
+
+
 def test_cfg2_full_volume_sampled(gpu):
     """The full 128^3 x 1024 x 16 volume in the benchmark's launch
     configuration, checked on sampled voxels computed one by one."""
