@@ -126,8 +126,12 @@ das_status das_plan_destroy(das_plan p);
 
 /* Replace c0 (m/s, > 0); read by the next enqueued call. */
 das_status das_plan_set_sound_speed(das_plan p, double c);
-/* Optional transmit weights w_tx[Q][N] f32 (device, caller-owned, must outlive
- * the calls that use it); NULL restores w_tx = 1. */
+/* Optional transmit weights: the factor w_tx of the weight w_qmn = w_tx_qn
+ * w_rx_mn (paragraph after Eq. (1); the transmit wavefield magnitude that
+ * Sec. 3.1 precomputes per voxel).  w_tx[Q][N] f32, device, caller-owned, must
+ * outlive the calls that use it; NULL restores w_tx = 1.  Transmits whose
+ * weight is zero over a whole voxel tile are skipped there (the sparse
+ * observation lists of Sec. 5); the result does not change. */
 das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
 /* Complex baseband (IQ) mode, the paper's data model (Sec. 2), with the phase
  * term that Eq. (2) omits for demodulated data: with enable != 0 the batch
@@ -179,19 +183,26 @@ das_status das_prepare(das_plan p, const float* y, int32_t b0, int32_t nb, int32
  * x: device [batch][N] f32, overwritten. */
 das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void* stream);
 
-/* Adjoint (exact transpose of das_forward as a map y -> x):
+/* Adjoint: the exact transpose of the linear map y -> x of Eq. (2), with the
+ * delays of Eq. (1) and linear interpolation (sentence after Eq. (2)):
  * gy[b][q][m][j] = sum_n w_qmn ((1-a)[j = k] + a [j = k+1]) gx[b][n].
- * gx: device [batch][N] f32; gy: device [batch][Q][M][K] f32, overwritten. */
+ * gx: device [batch][N] f32; gy: device [batch][Q][M][K] f32, overwritten
+ * (taps outside [0, K) are dropped, as they read zero in the forward map).
+ * Summation order across voxel tiles is not fixed (FP32 rounding level). */
 das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, void* stream);
 
-/* dL/dc = sum_{b,n} gx[b][n] dx[b][n]/dc, with dx/dc = sum_{q,m} w (s(k+1)-s(k)) df/dc,
+/* Sound-speed gradient: the derivative of Eq. (2) in c0 through the delays of
+ * Eq. (1) (grid, t0 and weights do not depend on c0):
+ * dL/dc = sum_{b,n} gx[b][n] dx[b][n]/dc, with dx/dc = sum_{q,m} w (s(k+1)-s(k)) df/dc,
  * df/dc = -fs (D_tx + D_rx)/c^2 (right-hand slope at integer f).
  * y: device [batch][Q][M][K] f32 (caller layout); gx: device [batch][N] f32;
  * dLdc: device scalar f32, overwritten. */
 das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int32_t batch,
                                 float* dLdc, void* stream);
 
-/* Several forward passes in one persistent launch (the batched form): for
+/* Several forward passes in one persistent launch: the batched problem of
+ * Sec. 2 (many frames beamformed with shared geometry, Sec. 3.2) extended to
+ * plans of different grids and arrays.  For
  * i < count, plan plans[i] beamforms its prepared workspace ws[i] (batch[i]
  * items) into x[i] ([batch[i]][N_i] f32).  The launch walks one work list of
  * (plan, voxel tile or column, batch group) items with a fixed grid of
@@ -208,7 +219,9 @@ das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int
 das_status das_forward_batched(int32_t count, const das_plan* plans, const void* const* ws,
                                const int32_t* batch, float* const* x, void* stream);
 
-/* Time the candidate tile shapes of the TILED algorithm for `batch` items on
+/* Tile shapes picked by measurement, as Sec. 3.2 says they should be chosen
+ * ("determined by profiling").  Times the candidate tile shapes of the TILED
+ * algorithm for `batch` items on
  * `stream` (using scratch buffers it allocates and frees) and keep the fastest
  * for this plan.  Synchronizes the stream. */
 das_status das_autotune(das_plan p, int32_t batch, void* stream);
@@ -222,7 +235,8 @@ das_status das_plan_set_tile(das_plan p, int32_t tile_index);
 int32_t das_num_tile_shapes(void);
 das_status das_tile_shape(int32_t tile_index, int32_t dims[3]);
 
-/* Fractional sample indices f as the forward kernels form them (integer part
+/* The fractional sample index of Eq. (1) (f = tau fs, with the readings
+ * above) as the forward kernels form it (integer part
  * plus the FP32 tile-relative part, converted exactly to f64), for transmit q,
  * elements [m0, m1) and voxels [n0, n1).  f_out: device [m1-m0][n1-n0] f64.
  * Exposes the in-kernel delay formation to the delay-error test. */
@@ -230,8 +244,8 @@ das_status das_debug_delays(das_plan p, int32_t q, int32_t m0, int32_t m1, int32
                             double* f_out, void* stream);
 
 /* Rank-truncation (SVD) clutter filter and power Doppler of an ensemble: the
- * rank-truncation primitive the paper names beside the beamformer (Sec. 1,
- * Sec. 6).  x: device [T][N] f32, T frames of N voxels (for example the
+ * rank-truncation primitive the paper names beside the beamformer for
+ * clutter filtering in ultrafast pipelines (Sec. 1, Sec. 5).  x: device [T][N] f32, T frames of N voxels (for example the
  * output of das_forward for a batch of T frames), read as the Casorati matrix
  * S = x^T = U diag(sigma) V^T.  The filter keeps the singular components
  * k_lo .. k_hi-1 (0 <= k_lo < k_hi <= T; the k_lo largest are tissue
@@ -245,12 +259,13 @@ das_status das_debug_delays(das_plan p, int32_t q, int32_t m0, int32_t m1, int32
  * (k_hi - k_lo) and T - (k_hi - k_lo) at most 64 (DAS_ERR_UNSUPPORTED
  * otherwise; DAS_ERR_INVALID_ARG for bad sizes or NULL pointers).
  * Method: Gram matrix x x^T on the matrix cores (FP32, chunks merged in
- * FP64), FP64 parallel Jacobi eigen-decomposition, per-voxel projection.
+ * FP64); parallel cyclic Jacobi eigen-decomposition (T <= 256: FP32 in LDS,
+ * eigenvectors refined in FP64 across the cuts; T > 256: FP64 in global
+ * memory); per-voxel projection.
  * Runs on the calling thread's current device. */
 das_status das_clutter_workspace_bytes(int32_t T, size_t* bytes);
 das_status das_clutter_filter(const float* x, int32_t T, int64_t N, int32_t k_lo, int32_t k_hi,
                               float* sv, float* power, float* xf, void* ws, void* stream);
-
 const char* das_status_string(das_status st);
 const char* das_last_error(void);
 /* Library version string. */

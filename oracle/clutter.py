@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper lists GPU rank truncation for clutter filtering among the
-primitives that accompany its beamformer (Sec. 1, Sec. 6), without a formula.
+primitives that accompany its beamformer (Sec. 1, Sec. 5), without a formula.
 Reading taken (the standard Casorati-matrix filter of ultrafast Doppler):
 
 * the ensemble x[t][n] (T frames of N voxels) is arranged as the Casorati

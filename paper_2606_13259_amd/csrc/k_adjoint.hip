@@ -8,8 +8,9 @@
 // One workgroup owns a 256-voxel tile (the same tiles, culling and
 // tile-relative delays as the windowed forward kernel).  For each chunk of
 // elements it accumulates the tile's contributions in LDS windows of
-// (transmit, element) channels with LDS float atomics, then flushes every
-// nonzero window entry to global memory with one float atomic.  Neighbouring
+// (transmit, element) channels with LDS integer atomics on fixed-point sums
+// (below), then flushes every nonzero window entry to global memory with one
+// float atomic.  Neighbouring
 // voxels hit the same taps, so most of the scatter traffic stays in LDS.
 // The windows hold 32-bit fixed-point sums: LDS integer atomics run several
 // times faster than LDS float atomics on this chip.  Per (tile, transmit

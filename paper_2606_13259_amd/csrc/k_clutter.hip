@@ -1,6 +1,6 @@
 // Rank-truncation (SVD) clutter filter and power Doppler of a beamformed
 // ensemble: the rank-truncation primitive that the paper names beside its
-// beamformer (Sec. 1, Sec. 6).  The ensemble x[T][N] (T frames of N voxels)
+// beamformer (Sec. 1, Sec. 5).  The ensemble x[T][N] (T frames of N voxels)
 // is the Casorati matrix S = x^T (N x T); S = U diag(sigma) V^T; the filter
 // keeps the singular components k_lo .. k_hi-1 and the power Doppler image is
 // P[n] = (1/T) sum_t xf[t][n]^2.

@@ -311,6 +311,53 @@ def cfg5_data(device="cpu"):
     return g, s, simulate(g, s, c=1500.0, device=device)
 
 
+def motion_positions(s: Scatterers, frames: int, seed_base: int, lam: float):
+    """Scatterer positions of frames 0 .. frames-1 of the random walk that
+    ``displaced`` defines (frame f = displaced(s, f, seed_base, lam)),
+    accumulated frame by frame."""
+    pos = s.pos.copy()
+    out = [pos.copy()]
+    for f in range(1, frames):
+        r = np.random.default_rng(seed_base + f)
+        pos = pos + r.normal(0.0, lam / 40.0, size=pos.shape)
+        out.append(pos.copy())
+    return out
+
+
+CFG4_SEED_BASE = 5
+
+
+def cfg4_ensemble(frames: int = 256, device="cuda", which=None, g: Optional[Geometry] = None):
+    """Doppler-style ensemble at the cfg2 geometry: the cfg2 scatterers (200
+    targets, seed 3; 1e4 speckle, seed 4) moved by the per-frame random walk
+    N(0, (lambda/40)^2) per axis (seed 5 + frame), each frame simulated and
+    normalised like cfg2_data (frame 0 is the cfg2 frame).  Returns
+    (g, y[F, Q, M, K] float32 on `device`, frame numbers), F = frames, or
+    only the frames listed in ``which``."""
+    import torch
+    g = cfg2() if g is None else g
+    s = scatterers(g, 200, 10_000, seed_targets=3, seed_speckle=4)
+    lam = C_NOMINAL / FC
+    pos = motion_positions(s, frames, CFG4_SEED_BASE, lam)
+    ids = list(range(frames)) if which is None else [int(f) for f in which]
+    y = torch.empty(len(ids), g.Q, g.M, g.K, dtype=torch.float32, device=device)
+    for i, f in enumerate(ids):
+        y[i] = simulate(g, Scatterers(pos[f], s.amp), device=device)
+    return g, y, ids
+
+
+def cfg5_focus_grid(g: Optional[Geometry] = None, oversample: int = 4) -> Geometry:
+    """The cfg5 voxel grid sampled ``oversample`` times finer in depth over the
+    same depth range (64 x 64 x 64 * oversample voxels): the envelope of an
+    echo spans about one lambda/2 voxel in depth, so the autofocus criterion is
+    evaluated on this grid to resolve it."""
+    g = cfg5() if g is None else g
+    sp = list(g.grid_spacing)
+    sp[2] /= oversample
+    nx, ny, nz = g.grid_dims
+    return g.replace(grid_spacing=tuple(sp), grid_dims=(nx, ny, (nz - 1) * oversample + 1))
+
+
 def random_channel_data(g: Geometry, batch: int, seed: int, device="cpu"):
     """y[B, Q, M, K] float32, i.i.d. N(0, 1): a stress input for parity."""
     import torch

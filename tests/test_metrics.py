@@ -39,3 +39,22 @@ def test_envelope_db_error():
     mx, mean = metrics.envelope_db_error(e, r, floor_db=-40)
     assert mx == pytest.approx(0.1, abs=1e-9)       # the -100 dB voxel is excluded
     assert mean == pytest.approx(0.1 / 3, abs=1e-9)
+
+
+def test_focus_criterion_is_magnification_invariant_and_peaks_at_focus():
+    """sum e^4 / sum e^2 of a well-sampled Gaussian blob does not change when
+    the blob is magnified (its widths scaled, peak kept), and falls when the
+    blob is defocused (widths scaled with the energy kept, peak lowered)."""
+    z, yy, x = np.meshgrid(np.arange(64), np.arange(64), np.arange(64), indexing="ij")
+
+    def blob(sig, amp):
+        e = amp * np.exp(-0.5 * (((x - 31.7) / sig[0]) ** 2 + ((yy - 32.2) / sig[1]) ** 2
+                                 + ((z - 30.9) / sig[2]) ** 2))
+        return np.sqrt(e), np.zeros_like(e)          # |x~|^2 = e
+
+    sig = np.array([2.5, 3.0, 2.0])
+    base = oenv.focus_criterion(*blob(sig, 1.0))
+    assert base == pytest.approx(1.0 / 2 ** 1.5, rel=1e-6)     # exp^2 / exp over 3 Gaussians
+    assert oenv.focus_criterion(*blob(1.3 * sig, 1.0)) == pytest.approx(base, rel=1e-6)
+    # defocus: same energy spread over a 1.3x wider blob
+    assert oenv.focus_criterion(*blob(1.3 * sig, 1.3 ** -3)) < 0.5 * base
