@@ -39,6 +39,10 @@ Readings of what the paper leaves open (each is also listed in the design doc):
 * R8 sound-speed derivative: grid and w_rx do not depend on c; t0 is a time;
   d f / d c = -fs (D_tx + D_rx) / c^2; at integer f the right-hand slope
   s(k+1) - s(k) is used (consistent with k = floor(f)).
+* R15 higher-order interpolation (the paper allows other schemes after
+  Eq. (2)): ``interp="cubic"`` is the four-point Lagrange interpolant through
+  samples k-1, k, k+1, k+2 (k = floor(f), alpha = f - k), which reproduces
+  every cubic polynomial; taps outside [0, K) read zero as in R4.
 """
 from __future__ import annotations
 
@@ -53,7 +57,7 @@ APOD_UNIFORM, APOD_HANN = 0, 1
 __all__ = [
     "TX_NONE", "TX_PLANE", "TX_DIVERGING", "APOD_UNIFORM", "APOD_HANN",
     "voxel_positions", "transmit_path", "receive_path", "receive_weight",
-    "fractional_index", "sample", "forward", "adjoint", "dforward_dc",
+    "fractional_index", "sample", "tap_weights", "forward", "adjoint", "dforward_dc",
     "grad_sound_speed", "nonzero_counts", "forward_slabs_parallel",
 ]
 
@@ -144,6 +148,21 @@ def sample(trace, j):
     return np.where(inside[None], trace[:, q, jc], 0.0)
 
 
+def tap_weights(alpha, interp="linear"):
+    """[(offset, weight)] of the interpolant at fractional position alpha in
+    [0, 1) after sample k: linear (the sentence after Eq. (2)) or the
+    four-point Lagrange cubic (reading R15)."""
+    a = alpha
+    if interp == "linear":
+        return [(0, 1.0 - a), (1, a)]
+    if interp == "cubic":
+        return [(-1, -a * (a - 1.0) * (a - 2.0) / 6.0),
+                (0, (a + 1.0) * (a - 1.0) * (a - 2.0) / 2.0),
+                (1, -(a + 1.0) * a * (a - 2.0) / 2.0),
+                (2, (a + 1.0) * a * (a - 1.0) / 6.0)]
+    raise ValueError(f"unknown interpolation {interp!r}")
+
+
 def _terms(g, p, c, w_tx):
     """Per-voxel transmit paths and transmit weights."""
     d_tx = transmit_path(g, p)                                 # [Q, n]
@@ -152,12 +171,14 @@ def _terms(g, p, c, w_tx):
     return d_tx, wt
 
 
-def forward(y, g, voxels=None, w_tx=None, c=None) -> np.ndarray:
+def forward(y, g, voxels=None, w_tx=None, c=None, interp="linear") -> np.ndarray:
     """x[b, n] = sum_q sum_m w_qmn ((1-alpha) s(k) + alpha s(k+1)) (Eq. (2)).
 
     y: [B, Q, M, K] (any real dtype; promoted to float64).
     voxels: optional voxel indices (to evaluate a sample of the volume).
     w_tx: optional [Q, n] transmit weights for exactly those voxels.
+    interp: "linear" (Eq. (2)) or "cubic" (reading R15: the sum of the
+    four Lagrange tap weights times s(k-1) .. s(k+2)).
     Returns float64 [B, n]."""
     y = np.asarray(y, np.float64)
     if y.ndim == 3:
@@ -176,9 +197,15 @@ def forward(y, g, voxels=None, w_tx=None, c=None) -> np.ndarray:
         k = k.astype(np.int64)
         w = wt * w_rx[None, :]                                                      # [Q, n]
         trace = y[:, :, m, :]                                                       # [B, Q, K]
-        s1 = sample(trace, k)                                                       # [B, Q, n]
-        s2 = sample(trace, k + 1)
-        x += np.sum(w[None] * ((1.0 - alpha[None]) * s1 + alpha[None] * s2), axis=1)
+        if interp == "linear":
+            s1 = sample(trace, k)                                                   # [B, Q, n]
+            s2 = sample(trace, k + 1)
+            x += np.sum(w[None] * ((1.0 - alpha[None]) * s1 + alpha[None] * s2), axis=1)
+        else:
+            v = np.zeros((B, Q, p.shape[0]))
+            for off, coef in tap_weights(alpha, interp):
+                v += coef[None] * sample(trace, k + off)
+            x += np.sum(w[None] * v, axis=1)
     return x
 
 
@@ -193,12 +220,13 @@ class _OneElement:
         self.f_number = g.f_number
 
 
-def adjoint(gx, g, w_tx=None, c=None) -> np.ndarray:
+def adjoint(gx, g, w_tx=None, c=None, interp="linear") -> np.ndarray:
     """gy[b, q, m, j] = sum_n w ((1-alpha)[j = k] + alpha [j = k+1]) gx[b, n].
 
     The exact transpose of ``forward`` (reading R7); taps outside [0, K) are
     dropped, as they read zero in the forward map.  gx: [B, N] over the whole
-    grid.  Returns float64 [B, Q, M, K]."""
+    grid.  With interp="cubic" the four Lagrange taps of reading R15 are
+    scattered instead.  Returns float64 [B, Q, M, K]."""
     gx = np.asarray(gx, np.float64)
     if gx.ndim == 1:
         gx = gx[None]
@@ -218,7 +246,8 @@ def adjoint(gx, g, w_tx=None, c=None) -> np.ndarray:
         w = wt * w_rx[None, :]
         for b in range(B):
             for q in range(Q):
-                for tap, coef in ((k[q], w[q] * (1.0 - alpha[q])), (k[q] + 1, w[q] * alpha[q])):
+                for off, cf in tap_weights(alpha[q], interp):
+                    tap, coef = k[q] + off, w[q] * cf
                     ok = (tap >= 0) & (tap < K)
                     gy[b, q, m] += np.bincount(tap[ok], weights=coef[ok] * gx[b, ok], minlength=K)
     return gy
