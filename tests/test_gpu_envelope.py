@@ -55,13 +55,16 @@ def test_envelope_and_point_targets_cfg2(gpu, storage, max_db, mean_db):
 
 
 def test_autofocus_converges_to_scan_argmax(gpu):
-    """cfg5 (data simulated at 1500 m/s on the CPU), loss = envelope energy of
-    the full 64^3 volume, gradient loop from 1540 m/s bounded to [1480, 1560]:
-    it converges to the argmax of the oracle's brute-force scan of the same
-    loss over that range (tests/golden/autofocus_scan.json, written by
-    tests/golden/make_autofocus_scan.py from the oracle alone).  How close
-    that argmax is to 1500 m/s is reported, not asserted: on this geometry the
-    energy of a fixed voxel grid grows with the assumed speed."""
+    """cfg5 (data simulated at 1500 m/s on the CPU), focus criterion
+    L(c) = sum |x~|^4 / sum |x~|^2 over the cfg5 volume sampled 4x finer in
+    depth, slope-sign search from 1540 m/s within [1480, 1560]: it ends within
+    0.5 m/s of the maximum of the oracle's brute-force scan of the same
+    criterion (tests/golden/autofocus_scan.json, written by
+    tests/golden/make_autofocus_scan.py from the oracle alone), and that
+    maximum lies inside the interval, not on a bound.  Its distance from the
+    data's 1500 m/s is reported: on this geometry a speed error mostly rescales
+    the image in depth (plane waves and the array centre scale exactly), so
+    focus responds only weakly to c."""
     import json
     import os
     from paper_2606_13259_amd import autofocus
@@ -69,9 +72,21 @@ def test_autofocus_converges_to_scan_argmax(gpu):
     with open(os.path.join(os.path.dirname(__file__), "golden", "autofocus_scan.json")) as f:
         scan = json.load(f)
     c_best = scan["argmax_c"]
+    assert scan["interior"] and 1480.0 + 2.0 <= c_best <= 1560.0 - 2.0
     g, s, y = synth.cfg5_data(device="cpu")
-    plan = das.Plan(g, max_batch=2, storage="f32")
+    gf = synth.cfg5_focus_grid(g)
+    assert list(gf.grid_dims) == scan["grid"]["dims"]
+    plan = das.Plan(gf, max_batch=2, storage="f32")
     c_gpu, hist = autofocus.autofocus(plan, y.to(gpu), c0=1540.0, bounds=(1480.0, 1560.0))
-    say(f"  oracle scan argmax {c_best:.1f} m/s; autofocus {c_gpu:.2f} m/s after {len(hist)} steps "
-        f"(data speed 1500 m/s)")
+    # the GPU criterion at the scan's speeds agrees with the oracle's values
+    lanes = metrics.analytic_lanes(y.to(gpu)).contiguous()
+    for c in (1500.0, c_best, 1540.0):
+        L, _ = autofocus.value_and_slope(plan, lanes, c)
+        allc = scan["coarse_c"] + scan["fine_c"]
+        allL = scan["coarse_L"] + scan["fine_L"]
+        j = int(np.argmin(np.abs(np.asarray(allc) - c)))
+        if abs(allc[j] - c) < 1e-9:
+            assert L == pytest.approx(allL[j], rel=1e-4), c
+    say(f"  oracle scan argmax {c_best:.1f} m/s; autofocus {c_gpu:.2f} m/s after {len(hist)} "
+        f"evaluations (data speed 1500 m/s)")
     assert abs(c_gpu - c_best) <= 0.5
