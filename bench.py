@@ -22,14 +22,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = ("volumes/s at 128³ vox×1024 el×16 tx: FP32 vs FP16/MFMA at stated L2 error")
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.3e12 non-packed FP32
-# lane operations/s; one FMA counts 2 flops.  Packed-FP32 instructions are not
-# generated by this build, so this is the VALU ceiling of these kernels.
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# MI355X published peaks: FP32 vector 157.3 TFLOP/s (packed FMA), dense FP16
+# MFMA 2.5 PFLOP/s, HBM3E 8 TB/s.  Packed-FP32 instructions are not generated
+# by this build, so the kernels' own VALU ceiling is the non-packed rate:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane operations/s, 78.6
+# TFLOP/s counting an FMA as 2 flops; it is reported beside the published peak.
+VALU_PEAK_TFLOPS = 157.3
+VALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+MFMA_F16_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBS = 8000.0
-# Algorithmic work model (flops): per nonzero (voxel, element) pair, per
-# nonzero (pair, transmit) triple, per (triple, batch item).
-FLOPS_PER_PAIR, FLOPS_PER_TRIPLE, FLOPS_PER_ITEM = 25, 8, 4
+# Algorithmic work model (flops): 25 per nonzero (voxel, element) pair (receive
+# path and apodization), 12 per nonzero (pair, transmit) triple (index and
+# weight formation), 4 per (triple, batch item) (two taps: 2 FMAs).
+FLOPS_PER_PAIR, FLOPS_PER_TRIPLE, FLOPS_PER_ITEM = 25, 12, 4
+STORAGE_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "fp8": 1}
 
 
 def log(msg):
@@ -44,6 +50,51 @@ def work_counts(name):
 def algorithmic_flops(counts, batch):
     return (FLOPS_PER_PAIR * counts["pairs_nonzero"] + FLOPS_PER_TRIPLE * counts["triples_nonzero"]
             + FLOPS_PER_ITEM * counts["triples_nonzero"] * batch)
+
+
+def valu_roofline(flops, ms, kernel=None, traffic=None):
+    """Algorithmic flops per launch over the launch's mean duration, against
+    the published FP32 peak, with the non-packed ceiling beside it."""
+    achieved = flops / (ms * 1e-3) / 1e12
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
+           "nonpacked_peak": round(VALU_NONPACKED_TFLOPS, 1),
+           "frac_nonpacked": round(achieved / VALU_NONPACKED_TFLOPS, 4),
+           "kernel_ms": round(ms, 4), "flops_per_launch": int(flops)}
+    if kernel:
+        out["kernel"] = kernel
+    return out
+
+
+def mfma_roofline(counts, B, storage, g, ms, traffic=None, kernel=None):
+    """The matrix-core form: useful flops (2 MACs per nonzero triple and item)
+    against the dense FP16 MFMA peak, and algorithmic bytes (the stored
+    samples of every item in, the f32 volume out) against HBM."""
+    flops = FLOPS_PER_ITEM * counts["triples_nonzero"] * B
+    nbytes = B * (g.Q * g.M * g.K * STORAGE_BYTES[storage] + 4 * g.N)
+    t = ms * 1e-3
+    out = {"bound": "mfma", "achieved": round(flops / t / 1e12, 3), "peak": MFMA_F16_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(flops / t / 1e12 / MFMA_F16_PEAK_TFLOPS, 5),
+           "traffic": traffic, "kernel_ms": round(ms, 4), "useful_flops_per_launch": int(flops),
+           "hbm": {"achieved": round(nbytes / t / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
+                   "algorithmic_bytes_per_launch": int(nbytes)}}
+    if traffic:
+        out["traffic_over_algorithmic"] = round(traffic / nbytes, 2)
+    if kernel:
+        out["kernel"] = kernel
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def recorded_traffic(kernel, tile):
@@ -95,25 +146,34 @@ def time_form(torch, das, plan, y, steps, warmup):
     return wall, prep, fwd, x
 
 
+def oracle_sample(oracle, y_np, g, idx, workers):
+    """The FP64 oracle on the voxels idx of every item of y_np (process pool)."""
+    xo, used = oracle.forward_slabs_parallel(y_np, g, voxels=idx, workers=workers, chunk=512)
+    return xo, used
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=262144,
-                    help="voxels of the volume the CPU oracle evaluates")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20,
+                    help="voxels of the volume the CPU oracle evaluates (default: half the volume)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="f16,bf16,fp8",
                     help="extra storage forms to time after the FP32 headline ('' for none)")
+    ap.add_argument("--plain", default="1,8",
+                    help="batch sizes of the plain FP32 kernel forms ('' for none)")
     ap.add_argument("--batched", type=int, default=16,
                     help="frames per step for the batched form (0 = skip)")
     ap.add_argument("--ensemble", type=int, default=256,
-                    help="frames per step for the Doppler-ensemble MFMA form (0 = skip)")
+                    help="frames of the Doppler ensemble (motion frames; 0 = skip)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="skip timing the adjoint and sound-speed gradient (cfg5)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-sparse-tx", dest="sparse_tx", action="store_false",
                     help="skip the spatially selective transmit-weight forms")
+    ap.add_argument("--no-iq", dest="iq", action="store_false", help="skip the complex baseband form")
     ap.add_argument("--tile", type=int, default=None,
                     help="use this tile shape index instead of autotuning (profiling runs)")
     args = ap.parse_args()
@@ -133,9 +193,12 @@ def main():
 
     dev = torch.device("cuda:0")
     das.lib()
+    t_sim = time.perf_counter()
     log("simulating cfg2 channel data on the GPU")
     g, _, yq = synth.cfg2_data(device="cuda:0")
     y = yq[None].contiguous()
+    torch.cuda.synchronize()
+    log(f"  simulated in {time.perf_counter() - t_sim:.1f} s")
     counts = work_counts("cfg2")
 
     plan = das.Plan(g, max_batch=max(1, args.batched), storage="f32")
@@ -153,15 +216,10 @@ def main():
     value = 1000.0 / wall
     log(f"FP32: {wall:.3f} ms/step (prepare {prep_ms:.3f} ms, forward {fwd_ms:.3f} ms) -> {value:.1f} volumes/s")
 
-    flops = algorithmic_flops(counts, 1)
-    achieved = flops / (fwd_ms * 1e-3) / 1e12
     kernel = "tiled_forward<float,1,16,false>"
     tile = list(das.das_tile_shape(plan.tile()))
-    traffic = recorded_traffic(kernel, tile)
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
-                "traffic_unit": "bytes per launch", "kernel": kernel, "kernel_ms": round(fwd_ms, 4),
-                "flops_per_launch": flops}
+    roofline = valu_roofline(algorithmic_flops(counts, 1), fwd_ms, kernel, recorded_traffic(kernel, tile))
+    roofline["traffic_unit"] = "bytes per launch"
     prep_bytes = 2 * 4 * g.Q * g.M * g.K
     reorder = {"bound": "hbm", "achieved": round(prep_bytes / (prep_ms * 1e-3) / 1e9, 1),
                "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -170,35 +228,38 @@ def main():
 
     # --- oracle on a bounded sample of voxels: stated L2 error + CPU baseline
     rng = np.random.default_rng(1234)
-    idx = np.sort(rng.choice(g.N, size=args.cpu_sample, replace=False))
-    xs = {"f32_b1": x[0, torch.from_numpy(idx).to(dev)].cpu().numpy()}
+    idx = np.sort(rng.choice(g.N, size=min(args.cpu_sample, g.N), replace=False))
+    idx_t = torch.from_numpy(idx).to(dev)
+    xs = {"f32_b1": x[0, idx_t].cpu().numpy()}
     cpu_baseline = None
     xo = None
+    workers = min(16, os.cpu_count() or 1)
     if not args.no_cpu_baseline:
         import oracle
-        workers = min(16, os.cpu_count() or 1)
-        log(f"oracle: {args.cpu_sample} voxels x {g.M} elements x {g.Q} transmits on {workers} processes")
+        log(f"oracle: {idx.size} voxels x {g.M} elements x {g.Q} transmits on {workers} processes")
         yc = y.cpu().numpy()
         t0 = time.perf_counter()
-        xo, used = oracle.forward_slabs_parallel(yc, g, voxels=idx, workers=workers, chunk=512)
+        xo, used = oracle_sample(oracle, yc, g, idx, workers)
         t_cpu = time.perf_counter() - t0
         xo = xo[0]
-        per_volume = t_cpu * g.N / args.cpu_sample
+        per_volume = t_cpu * g.N / idx.size
         cpu_baseline = {"value": round(1.0 / per_volume, 6), "unit": "volumes/s", "cores": used,
-                        "kind": "oracle",
-                        "sample": f"{args.cpu_sample} random voxels of the 128^3 volume, all 1024 "
-                                  f"elements x 16 transmits (FP64 NumPy, process pool); "
-                                  f"{t_cpu:.1f} s wall, scaled by N/sample"}
+                        "kind": "oracle", "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+                        "sample": f"{idx.size} random voxels ({idx.size / g.N:.3f} of the 128^3 "
+                                  f"volume), all 1024 elements x 16 transmits (FP64 NumPy, process "
+                                  f"pool of {used}); {t_cpu:.1f} s wall, scaled by N/sample"}
         log(f"oracle: {t_cpu:.1f} s -> {1.0 / per_volume:.2e} volumes/s")
 
-    def rel(v):
-        if xo is None:
+    def rel(v, ref=None):
+        ref = xo if ref is None else ref
+        if ref is None:
             return None
-        return float(np.linalg.norm(v - xo) / np.linalg.norm(xo))
+        return float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
 
     forms = {}
 
-    def run_form(name, storage, algo, yb, steps, note=None, w_tx=None, iq_fc=None):
+    def run_form(name, storage, algo, yb, steps, note=None, w_tx=None, iq_fc=None, roof=None,
+                 check=True):
         B = yb.shape[0]
         pf = das.Plan(g, max_batch=B, storage=storage, algo=algo)
         if pf.algo(B) == "tiled":
@@ -208,20 +269,32 @@ def main():
         if iq_fc is not None:
             pf.set_iq(iq_fc)
         wf, prf, fwf, xf = time_form(torch, das, pf, yb, steps, 1)
-        forms[name] = {"volumes_per_s": round(1000.0 * B / wf, 2), "ms_per_step": round(wf, 4),
-                       "forward_ms": round(fwf, 4), "prepare_ms": round(prf, 4), "batch": B,
-                       "storage": storage, "algo": pf.algo(B),
-                       "rel_l2": None if (w_tx is not None or iq_fc is not None) else
-                       rel(xf[0, torch.from_numpy(idx).to(dev)].cpu().numpy())}
+        f = {"volumes_per_s": round(1000.0 * B / wf, 2), "ms_per_step": round(wf, 4),
+             "forward_ms": round(fwf, 4), "prepare_ms": round(prf, 4), "batch": B,
+             "storage": storage, "algo": pf.algo(B),
+             "rel_l2": rel(xf[0, idx_t].cpu().numpy()) if check else None}
+        if roof == "valu":
+            f["roofline"] = valu_roofline(algorithmic_flops(counts, B), fwf)
+        elif roof == "mfma":
+            f["roofline"] = mfma_roofline(counts, B, storage, g, fwf)
         if note:
-            forms[name]["data"] = note
+            f["data"] = note
+        forms[name] = f
         log(f"{name}: {wf:.3f} ms/step (forward {fwf:.3f} ms) -> {1000.0 * B / wf:.1f} volumes/s "
             f"[{pf.algo(B)}]")
         pf.close()
-        del xf
+        return xf
 
     for st in [s for s in args.forms.split(",") if s]:
-        run_form(f"{st}_b1", st, "auto", y, max(3, args.steps // 2))
+        del_x = run_form(f"{st}_b1", st, "auto", y, max(3, args.steps // 2), roof="valu")
+        del del_x
+    # The plain kernel (per-voxel gathers from the caller's layout, no window
+    # staging, no aperture culling): the baseline of the windowed kernel.
+    for pb in [int(s) for s in args.plain.split(",") if s]:
+        yb = y.expand(pb, -1, -1, -1).contiguous() if pb > 1 else y
+        del_x = run_form(f"f32_plain_b{pb}", "f32", "plain", yb, 3, roof="valu",
+                         note=None if pb == 1 else "the simulated frame repeated")
+        del del_x, yb
     if args.sparse_tx:
         # A spatially selective transmit sequence (each transmit weighs one
         # lateral cell of a 4 x 4 layout, widened and tapered, zero elsewhere):
@@ -231,109 +304,41 @@ def main():
         note = (f"transmit weights: spatially selective, {float((wsel > 0).float().mean()):.3f} of "
                 f"(transmit, voxel) pairs nonzero")
         run_form("f32_b1_tx_weights_all_live", "f32", "auto", y, max(3, args.steps // 2), note=note,
-                 w_tx=wsel.clamp_min(1e-30).contiguous())
+                 w_tx=wsel.clamp_min(1e-30).contiguous(), check=False)
         run_form("f32_b1_tx_weights_sparse", "f32", "auto", y, max(3, args.steps // 2), note=note,
-                 w_tx=wsel)
+                 w_tx=wsel, check=False)
         del wsel
-    # Complex baseband: the simulated frame made analytic and demodulated at
-    # 7.5 MHz, one complex volume per step as an (I, Q) pair.
-    from paper_2606_13259_amd import metrics
-    za = metrics.analytic_lanes(y[0])
-    tk = g.t0 + torch.arange(g.K, device=dev, dtype=torch.float64) / g.fs
-    ph = -2.0 * np.pi * 7.5e6 * tk
-    yiq = torch.stack([za[0] * torch.cos(ph).float() - za[1] * torch.sin(ph).float(),
-                       za[0] * torch.sin(ph).float() + za[1] * torch.cos(ph).float()]).contiguous()
-    run_form("f32_iq_b1", "f32", "tiled", yiq, max(3, args.steps // 2), iq_fc=7.5e6,
-             note="IQ: the simulated frame, analytic and demodulated at 7.5 MHz; one complex volume "
-                  "per step (batch = the I and Q records)")
-    forms["f32_iq_b1"]["volumes_per_s"] = round(forms["f32_iq_b1"]["volumes_per_s"] / 2, 2)
-    forms["f32_iq_b1"]["unit_note"] = "complex volumes/s"
-    del za, yiq
+    if args.iq:
+        # Complex baseband: the simulated frame made analytic and demodulated at
+        # 7.5 MHz, one complex volume per step as an (I, Q) pair.
+        from paper_2606_13259_amd import metrics
+        za = metrics.analytic_lanes(y[0])
+        tk = g.t0 + torch.arange(g.K, device=dev, dtype=torch.float64) / g.fs
+        ph = -2.0 * np.pi * 7.5e6 * tk
+        yiq = torch.stack([za[0] * torch.cos(ph).float() - za[1] * torch.sin(ph).float(),
+                           za[0] * torch.sin(ph).float() + za[1] * torch.cos(ph).float()]).contiguous()
+        run_form("f32_iq_b1", "f32", "tiled", yiq, max(3, args.steps // 2), iq_fc=7.5e6, check=False,
+                 note="IQ: the simulated frame, analytic and demodulated at 7.5 MHz; one complex volume "
+                      "per step (batch = the I and Q records)")
+        forms["f32_iq_b1"]["volumes_per_s"] = round(forms["f32_iq_b1"]["volumes_per_s"] / 2, 2)
+        forms["f32_iq_b1"]["unit_note"] = "complex volumes/s"
+        del za, yiq
     if args.batched > 1:
         B = args.batched
         yb = y.expand(B, -1, -1, -1).contiguous()
         steps = max(2, args.steps // 4)
-        run_form(f"f32_tiled_b{B}", "f32", "tiled", yb, steps)
-        run_form(f"f16_tiled_b{B}", "f16", "tiled", yb, steps)
-        run_form(f"f16_mfma_b{B}", "f16", "mfma", yb, steps)
-        run_form(f"bf16_mfma_b{B}", "bf16", "mfma", yb, steps)
-        run_form(f"fp8_mfma_b{B}", "fp8", "mfma", yb, steps)
+        note = "the simulated frame repeated"
+        for name, st, algo, roof in ((f"f32_tiled_b{B}", "f32", "tiled", "valu"),
+                                     (f"f16_tiled_b{B}", "f16", "tiled", "valu"),
+                                     (f"f16_mfma_b{B}", "f16", "mfma", "mfma"),
+                                     (f"bf16_mfma_b{B}", "bf16", "mfma", "mfma"),
+                                     (f"fp8_mfma_b{B}", "fp8", "mfma", "mfma")):
+            del_x = run_form(name, st, algo, yb, steps, roof=roof, note=note)
+            del del_x
         del yb
+    torch.cuda.empty_cache()
     if args.ensemble > 1:
-        B = args.ensemble
-        yb = y.expand(B, -1, -1, -1).contiguous()
-        run_form(f"f16_mfma_b{B}", "f16", "mfma", yb, max(2, args.steps // 8),
-                 note="the simulated frame repeated (timing does not depend on the values)")
-        run_form(f"fp8_mfma_b{B}", "fp8", "mfma", yb, max(2, args.steps // 8),
-                 note="the simulated frame repeated (timing does not depend on the values)")
-        # The ensemble plus a mixed batch of grids and arrays in ONE persistent launch.
-        def run_persistent(name, storage):
-            mixed = synth.mixed_geometries()
-            mb = 16
-            plans = [das.Plan(g, max_batch=B, storage=storage)]
-            wss = [plans[0].prepare(yb)]
-            batches = [B]
-            for gm in mixed:
-                pm = das.Plan(gm, max_batch=mb, storage=storage)
-                torch.manual_seed(70)
-                wss.append(pm.prepare(torch.randn(mb, gm.Q, gm.M, gm.K, device=dev)))
-                plans.append(pm)
-                batches.append(mb)
-            outs = [torch.empty(b, p.N, dtype=torch.float32, device=dev) for p, b in zip(plans, batches)]
-            handles = [p.handle for p in plans]
-            das.das_forward_batched(handles, wss, batches, outs)
-            stream = torch.cuda.current_stream()
-            reps = max(2, args.steps // 8)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record(stream)
-            for _ in range(reps):
-                das.das_forward_batched(handles, wss, batches, outs)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            nvol = sum(batches)
-            forms[name] = {
-                "volumes_per_s": round(1000.0 * nvol / ms, 2), "launch_ms": round(ms, 3),
-                "volumes_per_launch": nvol, "storage": storage, "algo": plans[0].algo(B),
-                "plans": [{"grid": list(p.geom.grid_dims), "elements": p.M, "batch": b}
-                          for p, b in zip(plans, batches)],
-                "latency_note": "every frame of a launch completes when the launch does: per-frame "
-                                "latency = launch_ms",
-                "data": "ensemble: the simulated frame repeated; mixed grids: random N(0,1) data"}
-            log(f"{name}: {ms:.2f} ms per launch, {nvol} volumes -> {1000.0 * nvol / ms:.1f} volumes/s")
-            del wss, outs
-            for p in plans:
-                p.close()
-            torch.cuda.empty_cache()
-
-        run_persistent("persistent_ensemble_mixed", "f16")
-        run_persistent("persistent_ensemble_mixed_fp8", "fp8")
-        del yb
-        torch.cuda.empty_cache()
-        # Rank-truncation clutter filter + power Doppler over a 256-frame
-        # ensemble of 128^3 volumes (synthetic: rank-3 tissue clutter 40 dB
-        # above blood in a vessel, noise), tissue components 0..2 removed.
-        xe, _ = synth.doppler_ensemble_device((128, 128, 128), T=B, seed=11, device=dev)
-        wsc = torch.empty(das.das_clutter_workspace_bytes(B), dtype=torch.uint8, device=dev)
-        svc = torch.empty(B, device=dev)
-        pwc = torch.empty(xe.shape[1], device=dev)
-        das.das_clutter_filter(xe, 3, B, svc, pwc, None, wsc)
-        reps = max(2, args.steps // 8)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(reps):
-            das.das_clutter_filter(xe, 3, B, svc, pwc, None, wsc)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        forms["clutter_filter_power_doppler"] = {
-            "ms_per_ensemble": round(ms, 3), "frames": B, "voxels": int(xe.shape[1]),
-            "frames_per_s": round(1000.0 * B / ms, 1), "components_removed": 3,
-            "data": "synthetic ensemble: rank-3 tissue clutter 40 dB above blood in a vessel, noise"}
-        log(f"clutter filter + power Doppler: {B} frames x 128^3 in {ms:.2f} ms")
-        del xe, wsc
+        run_ensemble(args, torch, np, das, synth, g, counts, forms, workers)
     torch.cuda.empty_cache()
 
     if args.adjoint:
@@ -380,7 +385,7 @@ def main():
                    "batch": 1, "storage": "f32", "algo": plan.algo(1),
                    "tile": list(das.das_tile_shape(plan.tile()))},
         "rel_l2": rel(xs["f32_b1"]),
-        "rel_l2_sample_voxels": args.cpu_sample,
+        "rel_l2_sample_voxels": int(idx.size),
         "roofline": roofline,
         "reorder_roofline": reorder,
         "cpu_baseline": cpu_baseline,
@@ -390,6 +395,155 @@ def main():
         "dense_updates_per_s": round(g.N * g.M * g.Q / (wall * 1e-3), 1),
     }
     print(json.dumps(out), flush=True)
+
+
+def run_ensemble(args, torch, np, das, synth, g, counts, forms, workers):
+    """The Doppler ensemble: 256 frames whose scatterers move by a seeded
+    sub-wavelength random walk per frame, beamformed by the MFMA form (f16 and
+    FP8 storage), then alone and with the mixed grids in one persistent
+    launch, and finally through the clutter filter and power Doppler."""
+    import oracle
+    dev = torch.device("cuda:0")
+    B = args.ensemble
+    t0 = time.perf_counter()
+    log(f"simulating {B} motion frames on the GPU")
+    _, ye, _ = synth.cfg4_ensemble(B, device=dev, progress=lambda d, n: log(
+        f"  {d}/{n} frames ({time.perf_counter() - t0:.1f} s)"))
+    torch.cuda.synchronize()
+    log(f"  simulated in {time.perf_counter() - t0:.1f} s")
+    note = ("motion ensemble: the 200 targets + 1e4 speckle scatterers moved by a random walk "
+            "N(0, (lambda/40)^2) per axis per frame (seed 5 + frame)")
+    check = sorted({0, 1, B // 2, B - 1})
+    idx = np.sort(np.random.default_rng(99).choice(g.N, size=2048, replace=False))
+    idx_t = torch.from_numpy(idx).to(dev)
+    xo = None
+    if not args.no_cpu_baseline:
+        xo, _ = oracle_sample(oracle, ye[check].cpu().numpy(), g, idx, workers)
+    for st in ("f16", "fp8"):
+        pf = das.Plan(g, max_batch=B, storage=st)
+        wf, prf, fwf, xf = time_form(torch, das, pf, ye, max(2, args.steps // 8), 1)
+        f = {"volumes_per_s": round(1000.0 * B / wf, 2), "ms_per_step": round(wf, 4),
+             "forward_ms": round(fwf, 4), "prepare_ms": round(prf, 4), "batch": B, "storage": st,
+             "algo": pf.algo(B), "per_frame_latency_ms": round(wf, 3), "data": note,
+             "roofline": mfma_roofline(counts, B, st, g, fwf)}
+        if xo is not None:
+            xs = xf[check][:, idx_t].cpu().numpy()
+            f["rel_l2_frames"] = {str(fr): float(np.linalg.norm(xs[i] - xo[i]) / np.linalg.norm(xo[i]))
+                                  for i, fr in enumerate(check)}
+            f["rel_l2_sample_voxels"] = int(idx.size)
+        forms[f"{st}_mfma_b{B}"] = f
+        log(f"{st}_mfma_b{B}: {wf:.2f} ms/step (forward {fwf:.2f} ms) -> {1000.0 * B / wf:.1f} volumes/s "
+            f"[{pf.algo(B)}] rel-L2 {f.get('rel_l2_frames')}")
+        pf.close()
+        del xf
+    torch.cuda.empty_cache()
+
+    # The ensemble plus a mixed batch of grids and arrays in ONE persistent launch.
+    def run_persistent(name, storage):
+        mixed = synth.mixed_geometries()
+        mb = 16
+        plans = [das.Plan(g, max_batch=B, storage=storage)]
+        wss = [plans[0].prepare(ye)]
+        batches = [B]
+        for gm in mixed:
+            pm = das.Plan(gm, max_batch=mb, storage=storage)
+            torch.manual_seed(70)
+            wss.append(pm.prepare(torch.randn(mb, gm.Q, gm.M, gm.K, device=dev)))
+            plans.append(pm)
+            batches.append(mb)
+        outs = [torch.empty(b, p.N, dtype=torch.float32, device=dev) for p, b in zip(plans, batches)]
+        handles = [p.handle for p in plans]
+        das.das_forward_batched(handles, wss, batches, outs)
+        stream = torch.cuda.current_stream()
+        reps = max(2, args.steps // 8)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            das.das_forward_batched(handles, wss, batches, outs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nvol = sum(batches)
+        forms[name] = {
+            "volumes_per_s": round(1000.0 * nvol / ms, 2), "launch_ms": round(ms, 3),
+            "volumes_per_launch": nvol, "storage": storage, "algo": plans[0].algo(B),
+            "plans": [{"grid": list(p.geom.grid_dims), "elements": p.M, "batch": b}
+                      for p, b in zip(plans, batches)],
+            "latency_note": "every frame of a launch completes when the launch does: per-frame "
+                            "latency = launch_ms",
+            "data": "ensemble: the motion frames; mixed grids: random N(0,1) data"}
+        log(f"{name}: {ms:.2f} ms per launch, {nvol} volumes -> {1000.0 * nvol / ms:.1f} volumes/s")
+        del wss, outs
+        for p in plans:
+            p.close()
+        torch.cuda.empty_cache()
+
+    run_persistent("persistent_ensemble_mixed", "f16")
+    run_persistent("persistent_ensemble_mixed_fp8", "fp8")
+
+    # End to end: reorder + beamform the motion frames (f16 MFMA), then the
+    # rank-truncation clutter filter (3 tissue components removed) and power
+    # Doppler over the 256 volumes.
+    pf = das.Plan(g, max_batch=B, storage="f16")
+    ws = pf.workspace(B)
+    xe = torch.empty(B, g.N, dtype=torch.float32, device=dev)
+    wsc = torch.empty(das.das_clutter_workspace_bytes(B), dtype=torch.uint8, device=dev)
+    svc = torch.empty(B, device=dev)
+    pwc = torch.empty(g.N, device=dev)
+
+    def pipeline():
+        das.das_prepare(pf.handle, ye, 0, B, B, ws)
+        das.das_forward(pf.handle, ws, B, xe)
+        das.das_clutter_filter(xe, 3, B, svc, pwc, None, wsc)
+
+    pipeline()
+    reps = max(2, args.steps // 8)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+    torch.cuda.synchronize()
+    for i in range(reps):
+        ev[i][0].record()
+        das.das_prepare(pf.handle, ye, 0, B, B, ws)
+        ev[i][1].record()
+        das.das_forward(pf.handle, ws, B, xe)
+        ev[i][2].record()
+        das.das_clutter_filter(xe, 3, B, svc, pwc, None, wsc)
+        ev[i][3].record()
+    torch.cuda.synchronize()
+    part = [sum(e[j].elapsed_time(e[j + 1]) for e in ev) / reps for j in range(3)]
+    tot = sum(part)
+    forms["doppler_pipeline"] = {
+        "frames": B, "voxels": int(g.N), "storage": "f16", "algo": pf.algo(B),
+        "prepare_ms": round(part[0], 3), "forward_ms": round(part[1], 3),
+        "clutter_filter_ms": round(part[2], 3), "total_ms": round(tot, 3),
+        "frames_per_s": round(1000.0 * B / tot, 1), "components_removed": 3, "data": note}
+    log(f"doppler pipeline: {B} frames: prepare {part[0]:.2f} + forward {part[1]:.2f} + clutter "
+        f"{part[2]:.2f} = {tot:.2f} ms")
+    pf.close()
+    del ye, ws, xe, wsc
+    torch.cuda.empty_cache()
+
+    # The clutter filter alone on a synthetic ensemble with a vessel (rank-3
+    # tissue clutter 40 dB above blood, noise), 256 frames x 128^3.
+    xe, _ = synth.doppler_ensemble_device((128, 128, 128), T=B, seed=11, device=dev)
+    wsc = torch.empty(das.das_clutter_workspace_bytes(B), dtype=torch.uint8, device=dev)
+    svc = torch.empty(B, device=dev)
+    pwc = torch.empty(xe.shape[1], device=dev)
+    das.das_clutter_filter(xe, 3, B, svc, pwc, None, wsc)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        das.das_clutter_filter(xe, 3, B, svc, pwc, None, wsc)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    forms["clutter_filter_power_doppler"] = {
+        "ms_per_ensemble": round(ms, 3), "frames": B, "voxels": int(xe.shape[1]),
+        "frames_per_s": round(1000.0 * B / ms, 1), "components_removed": 3,
+        "data": "synthetic ensemble: rank-3 tissue clutter 40 dB above blood in a vessel, noise"}
+    log(f"clutter filter + power Doppler: {B} frames x 128^3 in {ms:.2f} ms")
+    del xe, wsc
 
 
 if __name__ == "__main__":

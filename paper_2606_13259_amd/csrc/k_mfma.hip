@@ -150,49 +150,60 @@ __device__ inline int row_max(int v) {
   return v;
 }
 
-// Depth-stacked form: one wavefront owns ZS voxel groups stacked in depth
-// (a 4 x 4 x ZS column) for 16 NB batch columns.  Per receiver row it loads the
-// union of the groups' chunks once, and applies to each loaded chunk the A
-// fragments of the groups that have taps in it (a wave-uniform test per
-// (group, chunk)), so a chunk read from L2 serves up to ZS groups.  Delays are
-// formed relative to the column centre.  The per-transmit delay terms (and
-// transmit weights) of a group of QN transmits live in LDS (bq_lds: QN x 64
-// lanes x ZS floats per wavefront, each lane reading only its own entries),
-// which keeps them out of the register budget of the chunk loop.
-template <class S, int ZS, int NB, int QN, bool WTX>
+// Box form: one wavefront owns a box of ZS = GX GY GZ voxel groups (GX x GY
+// lateral groups of 4 x 4 voxels, GZ depths) for 16 NB batch columns.  Per
+// receiver row it loads the union of the groups' chunks once, and applies to
+// each loaded chunk the A fragments of the groups that have taps in it (a
+// wave-uniform test per (group, chunk)), so a chunk read from L2 serves up to
+// ZS groups: lateral neighbours at one depth take their taps from nearly the
+// same samples, depth neighbours from samples about half a chunk apart per
+// voxel.  Delays are formed relative to the box centre.  The per-transmit
+// delay terms (and transmit weights) of a group of QN transmits live in LDS
+// (bq_lds: QN x 64 lanes x ZS floats per wavefront, each lane reading only its
+// own entries), which keeps them out of the register budget of the chunk loop.
+template <int X, int Y, int Z>
+struct Box {
+  static constexpr int GX = X, GY = Y, GZ = Z, ZS = X * Y * Z;
+};
+
+template <class S, class BX, int NB, int QN, bool WTX>
 __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ ws, int B, int TW,
                                            int Kc, float* __restrict__ x, int ngx, int ngy,
                                            int col, int by, float* __restrict__ bq_lds) {
   using T = typename Operand<S>::T;
-  constexpr int NCH = ZS / 2 + 2;  // chunks loaded per step before the rare second pass
+  constexpr int GX = BX::GX, GY = BX::GY, GZ = BX::GZ, ZS = BX::ZS;
+  // chunks loaded per step before the rare second pass
+  constexpr int NCH = GZ == 1 ? 3 : GZ / 2 + 2;
   const int lane = threadIdx.x & 63;
   const int per_z = ngx * ngy;
-  const int gz0 = g.n[2] - ZS * (col / per_z + 1);  // first depth of the stack (deepest first)
-  const int gx = col % ngx, gy = (col / ngx) % ngy;
+  const int gz0 = g.n[2] - GZ * (col / per_z + 1);  // first depth of the box (deepest first)
+  const int bx0 = (col % ngx) * 4 * GX, by0 = ((col / ngx) % ngy) * 4 * GY;  // first voxel
   const int vi = lane & 15, row = lane >> 4;
-  const int ix = gx * 4 + (vi & 3), iy = gy * 4 + (vi >> 2);
   const int M = g.M, K = g.K;
   const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
   const int subs = TW / (16 * NB);
   const int tile = by / subs, col0 = (by - tile * subs) * 16 * NB;
 
+  const float hx = 0.5f * (4 * GX - 1), hy = 0.5f * (4 * GY - 1), hzv = 0.5f * (GZ - 1);
   double px, py, pz;
-  tile_ref_point(g, gx * 4 + 1.5, gy * 4 + 1.5, gz0 + 0.5 * (ZS - 1), px, py, pz);
+  tile_ref_point(g, bx0 + (double)hx, by0 + (double)hy, gz0 + (double)hzv, px, py, pz);
   const float sx = (float)g.s[0], sy = (float)g.s[1], sz = (float)g.s[2];
-  const float dx = ((float)(vi & 3) - 1.5f) * sx, dy = ((float)(vi >> 2) - 1.5f) * sy;
-  float dz[ZS], dp2[ZS];
+  float dx[ZS], dy[ZS], dz[ZS], dp2[ZS];
   int nk[ZS];
   bool ink[ZS];
 #pragma unroll
   for (int k = 0; k < ZS; ++k) {
-    dz[k] = ((float)k - 0.5f * (ZS - 1)) * sz;
-    dp2[k] = dx * dx + dy * dy + dz[k] * dz[k];
-    ink[k] = ix < g.n[0] && iy < g.n[1] && gz0 + k >= 0;
-    nk[k] = ink[k] ? grid_index(g, ix, iy, gz0 + k) : 0;
+    const int kx = k % GX, ky = (k / GX) % GY, kz = k / (GX * GY);
+    const int lx = 4 * kx + (vi & 3), ly = 4 * ky + (vi >> 2);
+    dx[k] = ((float)lx - hx) * sx;
+    dy[k] = ((float)ly - hy) * sy;
+    dz[k] = ((float)kz - hzv) * sz;
+    dp2[k] = dx[k] * dx[k] + dy[k] * dy[k] + dz[k] * dz[k];
+    ink[k] = bx0 + lx < g.n[0] && by0 + ly < g.n[1] && gz0 + kz >= 0;
+    nk[k] = ink[k] ? grid_index(g, bx0 + lx, by0 + ly, gz0 + kz) : 0;
   }
   const float fscf = (float)g.fsc;
-  const float hz = 0.5f * (ZS - 1) * sz;
-  const float Rg = sqrtf(2.25f * (sx * sx + sy * sy) + hz * hz);
+  const float Rg = sqrtf(hx * hx * sx * sx + hy * hy * sy * sy + hzv * hzv * sz * sz);
   const bool hann = g.apod == DAS_APOD_HANN_FNUM;
   const float cth = hann ? sqrtf(g.fourF2) * rsqrtf(1.f + g.fourF2) : -1.f;
   const float sth = hann ? rsqrtf(1.f + g.fourF2) : 0.f;
@@ -231,7 +242,7 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
       bool nz = false;
 #pragma unroll
       for (int k = 0; k < ZS; ++k) {
-        bql[q * 64 * PER + k] = fmaf(delta_tx(r, dx, dy, dz[k], dp2[k]), fscf, gq);
+        bql[q * 64 * PER + k] = fmaf(delta_tx(r, dx[k], dy[k], dz[k], dp2[k]), fscf, gq);
         if constexpr (WTX) {
           const float wt = (q < qn && ink[k]) ? g.w_tx[(size_t)(q0 + q) * N + nk[k]] : 0.f;
           bql[q * 64 * PER + ZS + k] = wt;
@@ -288,8 +299,8 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
         bool anyw = false;
 #pragma unroll
         for (int k = 0; k < ZS; ++k) {
-          w[k] = j < 0 ? 0.f : rx_weight(g, m, ex + dx, ey + dy, ez + dz[k]);
-          a[k] = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz[k], dp2[k]), fscf, h);
+          w[k] = j < 0 ? 0.f : rx_weight(g, m, ex + dx[k], ey + dy[k], ez + dz[k]);
+          a[k] = fmaf(delta_dist(ex, ey, ez, en, dx[k], dy[k], dz[k], dp2[k]), fscf, h);
           anyw |= w[k] != 0.f;
         }
         if (__ballot(anyw) == 0ull) continue;
@@ -373,8 +384,8 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
       }
     }
   }
-  const int jy = gy * 4 + row;
-  if (jy >= g.n[1]) return;
+  // lane (vi, row) holds rows 4 row .. 4 row + 3 of column vi of each tile:
+  // voxels (r, row) of each group, batch item vi of each tile
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int b = tile * TW + col0 + nb * 16 + vi;
@@ -383,11 +394,13 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
     if constexpr (__is_same(S, uint8_t)) e = fp8_item_exponent(g.amax[b]);
 #pragma unroll
     for (int k = 0; k < ZS; ++k) {
-      if (gz0 + k < 0) continue;
-      float* xb = x + (size_t)b * N + (size_t)g.n[0] * (jy + (size_t)g.n[1] * (gz0 + k));
+      const int kx = k % GX, ky = (k / GX) % GY, kz = k / (GX * GY);
+      const int jy = by0 + 4 * ky + row;
+      if (gz0 + kz < 0 || jy >= g.n[1]) continue;
+      float* xb = x + (size_t)b * N + (size_t)g.n[0] * (jy + (size_t)g.n[1] * (gz0 + kz));
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int jx = gx * 4 + r;
+        const int jx = bx0 + 4 * kx + r;
         if (jx < g.n[0]) {
           if constexpr (__is_same(S, uint8_t))
             xb[jx] = ldexpf(acc[k][nb][r], -e);
@@ -411,18 +424,20 @@ __device__ inline int xcd_remap(int b, int nblocks) {
   return r * per + (k % X) * C + k / X;
 }
 
-template <class T, int ZS, int NB, int QN, bool WTX>
+template <class T, class BX, int NB, int QN, bool WTX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 2 : 3))) void mfma_forward_stack(
     Geom g, const T* __restrict__ ws, int B, int TW, int Kc, float* __restrict__ x, int ngx,
     int ngy, int ncols) {
-  __shared__ __align__(16) float bq_lds[4 * QN * 64 * ZS * (WTX ? 2 : 1)];
+  __shared__ __align__(16) float bq_lds[4 * QN * 64 * BX::ZS * (WTX ? 2 : 1)];
   const int col = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (col >= ncols) return;  // whole wavefront
-  stack_body<T, ZS, NB, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y, bq_lds);
+  stack_body<T, BX, NB, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y, bq_lds);
 }
 
-// Voxel groups per wavefront column of the depth-stacked form.
-constexpr int kStack = 4;
+// Voxel groups per wavefront box: a 4 x 4 x 4 column (four 4 x 4 groups
+// stacked in depth).
+using kBox = Box<1, 1, 4>;
+constexpr int kStack = kBox::ZS;
 
 // Persistent form with dynamic scheduling.  Work items are (plan, wavefront
 // column, 16-item batch slice), plan i owning items first[i] .. first[i+1]-1
@@ -463,10 +478,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBMAX == 4 
     // each plan runs with its own batch tiles per wavefront (w.nb, uniform:
     // NBMAX or 1)
     if (w.nb == NBMAX)
-      stack_body<T, kStack, NBMAX, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc,
+      stack_body<T, kBox, NBMAX, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc,
                                             w.x, w.ngx, w.ngy, col, by, bq_lds);
     else
-      stack_body<T, kStack, 1, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
+      stack_body<T, kBox, 1, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
                                         w.ngx, w.ngy, col, by, bq_lds);
   }
 }
@@ -529,37 +544,37 @@ __global__ __launch_bounds__(256) void reorder_chunks(const float* __restrict__ 
   }
 }
 
-template <class T, int ZS, int NB, int QN, bool WTX>
+template <class T, class BX, int NB, int QN, bool WTX>
 hipError_t launch_stack_t(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
-  const int ngx = (g.n[0] + 3) / 4, ngy = (g.n[1] + 3) / 4;
-  const int ncols = ngx * ngy * ((g.n[2] + ZS - 1) / ZS);
+  const int ngx = (g.n[0] + 4 * BX::GX - 1) / (4 * BX::GX), ngy = (g.n[1] + 4 * BX::GY - 1) / (4 * BX::GY);
+  const int ncols = ngx * ngy * ((g.n[2] + BX::GZ - 1) / BX::GZ);
   const int TW = mfma_tile_width(B), Kc = mfma_chunks(g.K);
   dim3 grid((ncols + 3) / 4, mfma_batch_pad(B) / (16 * NB));
-  hipLaunchKernelGGL((mfma_forward_stack<T, ZS, NB, QN, WTX>), grid, dim3(256), 0, st, g,
+  hipLaunchKernelGGL((mfma_forward_stack<T, BX, NB, QN, WTX>), grid, dim3(256), 0, st, g,
                      static_cast<const T*>(ws), B, TW, Kc, x, ngx, ngy, ncols);
   return hipGetLastError();
 }
 
-template <class T, int ZS, int NB>
+template <class T, class BX, int NB>
 hipError_t launch_stack(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
-  constexpr int QMAX = ZS >= 8 ? 4 : 8;
+  constexpr int QMAX = BX::ZS >= 8 ? 4 : 8;
   const bool wtx = g.w_tx != nullptr;
   const int qg = g.Q == 1 ? 1 : (g.Q <= 4 || QMAX == 4) ? 4 : 8;
   if (qg == 1)
-    return wtx ? launch_stack_t<T, ZS, NB, 1, true>(g, ws, B, x, st)
-               : launch_stack_t<T, ZS, NB, 1, false>(g, ws, B, x, st);
+    return wtx ? launch_stack_t<T, BX, NB, 1, true>(g, ws, B, x, st)
+               : launch_stack_t<T, BX, NB, 1, false>(g, ws, B, x, st);
   if (qg == 4)
-    return wtx ? launch_stack_t<T, ZS, NB, 4, true>(g, ws, B, x, st)
-               : launch_stack_t<T, ZS, NB, 4, false>(g, ws, B, x, st);
-  return wtx ? launch_stack_t<T, ZS, NB, QMAX, true>(g, ws, B, x, st)
-             : launch_stack_t<T, ZS, NB, QMAX, false>(g, ws, B, x, st);
+    return wtx ? launch_stack_t<T, BX, NB, 4, true>(g, ws, B, x, st)
+               : launch_stack_t<T, BX, NB, 4, false>(g, ws, B, x, st);
+  return wtx ? launch_stack_t<T, BX, NB, QMAX, true>(g, ws, B, x, st)
+             : launch_stack_t<T, BX, NB, QMAX, false>(g, ws, B, x, st);
 }
 
 template <class T>
 hipError_t launch_any(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
-  if (mfma_stack_tiles(B) == 4) return launch_stack<T, kStack, 4>(g, ws, B, x, st);
-  if (mfma_stack_tiles(B) == 2) return launch_stack<T, kStack, 2>(g, ws, B, x, st);
-  return launch_stack<T, kStack, 1>(g, ws, B, x, st);
+  if (mfma_stack_tiles(B) == 4) return launch_stack<T, kBox, 4>(g, ws, B, x, st);
+  if (mfma_stack_tiles(B) == 2) return launch_stack<T, kBox, 2>(g, ws, B, x, st);
+  return launch_stack<T, kBox, 1>(g, ws, B, x, st);
 }
 
 template <class T, int QN, bool WTX, int NBMAX>
@@ -640,9 +655,9 @@ hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, i
     const int Q = w.g.Q;
     qn = std::max(qn, Q == 1 ? 1 : Q <= 4 ? 4 : 16);
     wtx |= w.g.w_tx != nullptr;
-    w.ngx = (w.g.n[0] + 3) / 4;
-    w.ngy = (w.g.n[1] + 3) / 4;
-    w.ngroups = w.ngx * w.ngy * ((w.g.n[2] + kStack - 1) / kStack);  // wavefront columns
+    w.ngx = (w.g.n[0] + 4 * kBox::GX - 1) / (4 * kBox::GX);
+    w.ngy = (w.g.n[1] + 4 * kBox::GY - 1) / (4 * kBox::GY);
+    w.ngroups = w.ngx * w.ngy * ((w.g.n[2] + kBox::GZ - 1) / kBox::GZ);  // wavefront boxes
     w.nbx = 0;
     w.nb = persistent_nb(storage, w.B);
     a.first[i + 1] = a.first[i] + w.ngroups * (mfma_batch_pad(w.B) / (16 * w.nb));
