@@ -266,6 +266,20 @@ das_status das_debug_delays(das_plan p, int32_t q, int32_t m0, int32_t m1, int32
 das_status das_clutter_workspace_bytes(int32_t T, size_t* bytes);
 das_status das_clutter_filter(const float* x, int32_t T, int64_t N, int32_t k_lo, int32_t k_hi,
                               float* sv, float* power, float* xf, void* ws, void* stream);
+
+/* das_clutter_filter for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation with its workspace in a buffer the
+ * library holds, a static device array of 12.4 MiB per device that lives
+ * until the process ends.  No allocation of any kind is made.  Arguments as
+ * for das_clutter_filter without ws; T <= 256 (DAS_ERR_INVALID_ARG above).
+ * Every call on a device shares that device's buffer: calls that overlap on
+ * one device (different streams or threads) race and must be serialised by
+ * the caller.  The buffer keeps the last call's contents; each call clears
+ * what it needs at zero. */
+das_status das_clutter_filter_noalloc(const float* x, int32_t T, int64_t N, int32_t k_lo,
+                                      int32_t k_hi, float* sv, float* power, float* xf,
+                                      void* stream);
 const char* das_status_string(das_status st);
 const char* das_last_error(void);
 /* Library version string. */

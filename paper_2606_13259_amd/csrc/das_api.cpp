@@ -715,23 +715,52 @@ das_status das_clutter_workspace_bytes(int32_t T, size_t* bytes) {
   return DAS_OK;
 }
 
-das_status das_clutter_filter(const float* x, int32_t T, int64_t N, int32_t k_lo, int32_t k_hi,
-                              float* sv, float* power, float* xf, void* ws, void* stream) {
-  if (!x || !sv || !power || !ws) return fail(DAS_ERR_INVALID_ARG, "x, sv, power or ws is NULL");
+static das_status check_clutter_args(const float* x, int32_t T, int64_t N, int32_t k_lo,
+                                     int32_t k_hi, const float* sv, const float* power) {
+  if (!x || !sv || !power) return fail(DAS_ERR_INVALID_ARG, "x, sv or power is NULL");
   if (T < 1 || T > 512) return fail(DAS_ERR_INVALID_ARG, "T must be in [1, 512]");
   if (N < 1) return fail(DAS_ERR_INVALID_ARG, "N must be >= 1");
   if (k_lo < 0 || k_hi <= k_lo || k_hi > T)
     return fail(DAS_ERR_INVALID_ARG, "need 0 <= k_lo < k_hi <= T");
   if (clutter_basis_size(T, k_lo, k_hi) > 64)
     return fail(DAS_ERR_UNSUPPORTED, "at most 64 components may be kept or removed");
+  return DAS_OK;
+}
+
+static das_status run_clutter(const float* x, int32_t T, int64_t N, int32_t k_lo, int32_t k_hi,
+                              float* sv, float* power, float* xf, void* ws, void* stream,
+                              const char* where) {
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   e = launch_clutter_filter(x, T, N, k_lo, k_hi, sv, power, xf, ws, cus,
                             static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "das_clutter_filter launch");
+  if (e != hipSuccess) return hip_fail(e, where);
   return DAS_OK;
+}
+
+das_status das_clutter_filter(const float* x, int32_t T, int64_t N, int32_t k_lo, int32_t k_hi,
+                              float* sv, float* power, float* xf, void* ws, void* stream) {
+  if (das_status s = check_clutter_args(x, T, N, k_lo, k_hi, sv, power)) return s;
+  if (!ws) return fail(DAS_ERR_INVALID_ARG, "ws is NULL");
+  return run_clutter(x, T, N, k_lo, k_hi, sv, power, xf, ws, stream, "das_clutter_filter launch");
+}
+
+das_status das_clutter_filter_noalloc(const float* x, int32_t T, int64_t N, int32_t k_lo,
+                                      int32_t k_hi, float* sv, float* power, float* xf,
+                                      void* stream) {
+  if (das_status s = check_clutter_args(x, T, N, k_lo, k_hi, sv, power)) return s;
+  if (T > clutter_static_max_frames())
+    return fail(DAS_ERR_INVALID_ARG, "das_clutter_filter_noalloc: T exceeds the static workspace (256 frames)");
+  void* ws = nullptr;
+  size_t bytes = 0;
+  hipError_t e = clutter_static_scratch(&ws, &bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress (static clutter workspace)");
+  if (clutter_workspace_bytes(T) > bytes)
+    return fail(DAS_ERR_INVALID_ARG, "das_clutter_filter_noalloc: workspace exceeds the static buffer");
+  return run_clutter(x, T, N, k_lo, k_hi, sv, power, xf, ws, stream,
+                     "das_clutter_filter_noalloc launch");
 }
 
 das_status das_debug_delays(das_plan p, int32_t q, int32_t m0, int32_t m1, int32_t n0, int32_t n1,

@@ -151,6 +151,8 @@ size_t tiled_lds_fp8(const Geom& g, int bt, const Window& w);
 
 // Rank-truncation clutter filter (k_clutter.hip).
 size_t clutter_workspace_bytes(int T);
+int clutter_static_max_frames();                              // T limit of the static workspace
+hipError_t clutter_static_scratch(void** ptr, size_t* bytes);  // this device's static workspace
 int clutter_basis_size(int T, int k_lo, int k_hi);  // components the projection uses
 hipError_t launch_clutter_filter(const float* x, int T, long long N, int k_lo, int k_hi, float* sv,
                                  float* pd, float* xf, void* ws, int cus, hipStream_t st);

@@ -24,6 +24,8 @@
 //      series is B a (keep form) or s_n - B a (removal form), whichever uses
 //      fewer components (at most 64), and P[n] its mean square.  Every voxel
 //      reads its T samples twice (from L2 or HBM); B sits in LDS.
+#include <mutex>
+
 #include "das_internal.h"
 
 namespace dasmi {
@@ -541,21 +543,55 @@ hipError_t launch_project(const float* x, int T, long long N, const float* Bm, i
   return hipGetLastError();
 }
 
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t rot_log_bytes(int T) {
+constexpr size_t rot_log_bytes(int T) {
   const int Tp = T + (T & 1);
   return align256(sizeof(Rot) * (size_t)kMaxSweeps * (Tp - 1) * (Tp / 2));
 }
 
-}  // namespace
-
-size_t clutter_workspace_bytes(int T) {
+constexpr size_t workspace_bytes(int T) {
   size_t b = 2 * align256(sizeof(double) * (size_t)T * T) + align256(sizeof(float) * (size_t)T * 64);
   if (T <= kFastT)
     b += rot_log_bytes(T) + align256(sizeof(float) * (size_t)T) + 256 +
          align256(sizeof(double) * (size_t)T * 64);
   return b;
+}
+
+// Workspace of the allocation-free entry point: room for ensembles of up to
+// kStaticT frames (12.4 MiB), one copy per device, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, not the device
+// array: its device address comes from hipGetSymbolAddress, once per device.
+constexpr int kStaticT = 256;
+constexpr size_t kStaticBytes = workspace_bytes(kStaticT);
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+}  // namespace
+
+size_t clutter_workspace_bytes(int T) { return workspace_bytes(T); }
+
+int clutter_static_max_frames() { return kStaticT; }
+
+// Device address of this device's copy of `scratch`, looked up on the first
+// call made with each device current and kept.
+hipError_t clutter_static_scratch(void** ptr, size_t* bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = kStaticBytes;
+  return hipSuccess;
 }
 
 int clutter_basis_size(int T, int k_lo, int k_hi) {

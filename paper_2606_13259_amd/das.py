@@ -102,6 +102,7 @@ def lib():
             "das_plan_set_iq": [_P, _I, ctypes.c_double],
             "das_clutter_workspace_bytes": [_I, ctypes.POINTER(ctypes.c_size_t)],
             "das_clutter_filter": [_P, _I, ctypes.c_int64, _I, _I, _P, _P, _P, _P, _P],
+            "das_clutter_filter_noalloc": [_P, _I, ctypes.c_int64, _I, _I, _P, _P, _P, _P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -230,6 +231,15 @@ def das_clutter_filter(x: torch.Tensor, k_lo: int, k_hi: int, sv: torch.Tensor, 
     N = x.numel() // T
     _check(lib().das_clutter_filter(_ptr(x), int(T), int(N), int(k_lo), int(k_hi), _ptr(sv), _ptr(power),
                                     _ptr(xf), _ptr(ws), _stream(x.device)), "das_clutter_filter")
+
+
+def das_clutter_filter_noalloc(x: torch.Tensor, k_lo: int, k_hi: int, sv: torch.Tensor,
+                               power: torch.Tensor, xf: Optional[torch.Tensor]):
+    T = x.shape[0]
+    N = x.numel() // T
+    _check(lib().das_clutter_filter_noalloc(_ptr(x), int(T), int(N), int(k_lo), int(k_hi), _ptr(sv),
+                                            _ptr(power), _ptr(xf), _stream(x.device)),
+           "das_clutter_filter_noalloc")
 
 
 def clutter_filter(x: torch.Tensor, k_lo: int, k_hi: Optional[int] = None, filtered: bool = False):
