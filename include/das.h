@@ -144,6 +144,17 @@ das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
  * DAS_ERR_INVALID_ARG otherwise); das_adjoint, das_grad_sound_speed and
  * das_forward_batched refuse IQ plans.  enable = 0 restores real data. */
 das_status das_plan_set_iq(das_plan p, int32_t enable, double fc);
+/* Interpolation of the channel samples at the fractional index f of Eq. (1):
+ * DAS_INTERP_LINEAR (0, the default) is Eq. (2); DAS_INTERP_CUBIC (1) is the
+ * four-point Lagrange interpolant through samples k-1 .. k+2 (k = floor(f)),
+ * one of the alternative schemes the paper allows after Eq. (2), with taps
+ * outside [0, K) reading zero as for linear interpolation.  Cubic runs in the
+ * windowed algorithm with f32 storage on real data: das_plan_set_interp
+ * returns DAS_ERR_UNSUPPORTED for a plan whose algorithm for some batch is
+ * not the windowed one, and das_forward (IQ plans), das_adjoint,
+ * das_grad_sound_speed and das_forward_batched refuse cubic plans. */
+typedef enum { DAS_INTERP_LINEAR = 0, DAS_INTERP_CUBIC = 1 } das_interp;
+das_status das_plan_set_interp(das_plan p, int32_t interp);
 /* Force an algorithm (das_algo) for subsequent calls; AUTO restores the
  * plan's choice.  AUTO depends only on the storage type, the batch size and
  * what was fixed at plan creation: MFMA for 16- or 8-bit storage with batch >= 16,

@@ -146,6 +146,7 @@ struct das_plan_s {
   // Complex baseband mode (das_plan_set_iq): carrier frequency (Hz).
   bool iq = false;
   double fc = 0.0;
+  int interp = DAS_INTERP_LINEAR;  // das_plan_set_interp
 };
 
 namespace {
@@ -208,6 +209,7 @@ hipError_t launch_windowed(const das_plan_s* p, const Geom& g, int tile, const v
   const TileShape ts = tile_shape(tile);
   const Window w = make_window(p, ts);
   if (p->iq) return tiled_forward_f32_iq(g, ts, w, ws, B, x, st);
+  if (p->interp == DAS_INTERP_CUBIC) return tiled_forward_f32_cubic(g, ts, w, ws, B, x, st);
   return launch_tiled_forward(g, p->cfg.storage, ts, w, ws, B, x, st);
 }
 
@@ -440,7 +442,25 @@ das_status das_plan_set_algo(das_plan p, int32_t algo) {
   if (algo < DAS_ALGO_AUTO || algo > DAS_ALGO_MFMA) return fail(DAS_ERR_INVALID_ARG, "unknown algo");
   if (algo == DAS_ALGO_MFMA && p->cfg.storage == DAS_STORE_F32)
     return fail(DAS_ERR_UNSUPPORTED, "the MFMA form needs f16, bf16 or fp8 storage");
+  if (p->interp == DAS_INTERP_CUBIC && (algo == DAS_ALGO_PLAIN || algo == DAS_ALGO_MFMA ||
+                                        (algo == DAS_ALGO_AUTO && !p->auto_tiled)))
+    return fail(DAS_ERR_UNSUPPORTED, "cubic interpolation runs in the windowed algorithm only");
   p->algo = algo;
+  return DAS_OK;
+}
+
+das_status das_plan_set_interp(das_plan p, int32_t interp) {
+  if (das_status s = check_plan(p)) return s;
+  if (interp != DAS_INTERP_LINEAR && interp != DAS_INTERP_CUBIC)
+    return fail(DAS_ERR_INVALID_ARG, "unknown interpolation");
+  if (interp == DAS_INTERP_CUBIC) {
+    if (p->cfg.storage != DAS_STORE_F32)
+      return fail(DAS_ERR_UNSUPPORTED, "cubic interpolation runs with f32 storage only");
+    const bool tiled = p->algo == DAS_ALGO_TILED || (p->algo == DAS_ALGO_AUTO && p->auto_tiled);
+    if (!tiled)
+      return fail(DAS_ERR_UNSUPPORTED, "cubic interpolation runs in the windowed algorithm only");
+  }
+  p->interp = interp;
   return DAS_OK;
 }
 
@@ -521,6 +541,8 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
   const Geom g = call_geom(p, ws, batch);
   const int algo = choose_algo(p, batch);
   hipError_t e = hipSuccess;
+  if (p->interp == DAS_INTERP_CUBIC && (p->iq || algo != DAS_ALGO_TILED))
+    return fail(DAS_ERR_UNSUPPORTED, "cubic interpolation runs in the windowed algorithm on real data");
   if (p->iq) {
     if (batch % 2) return fail(DAS_ERR_INVALID_ARG, "complex baseband needs (I, Q) pairs: an even batch");
     if (algo != DAS_ALGO_TILED || p->cfg.storage != DAS_STORE_F32)
@@ -545,6 +567,8 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
 das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, void* stream) {
   if (das_status s = check_plan(p)) return s;
   if (p->iq) return fail(DAS_ERR_UNSUPPORTED, "the adjoint of the complex baseband form is not built");
+  if (p->interp != DAS_INTERP_LINEAR)
+    return fail(DAS_ERR_UNSUPPORTED, "the adjoint is built for linear interpolation only");
   if (!gx || !gy) return fail(DAS_ERR_INVALID_ARG, "gx or gy is NULL");
   if (das_status s = check_batch(p, batch)) return s;
   DeviceGuard dg(p->device);
@@ -562,6 +586,8 @@ das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int
                                 float* dLdc, void* stream) {
   if (das_status s = check_plan(p)) return s;
   if (p->iq) return fail(DAS_ERR_UNSUPPORTED, "the gradient of the complex baseband form is not built");
+  if (p->interp != DAS_INTERP_LINEAR)
+    return fail(DAS_ERR_UNSUPPORTED, "the sound-speed gradient is built for linear interpolation only");
   if (!y || !gx || !dLdc) return fail(DAS_ERR_INVALID_ARG, "y, gx or dLdc is NULL");
   if (das_status s = check_batch(p, batch)) return s;
   DeviceGuard dg(p->device);
@@ -611,6 +637,8 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
       return fail(DAS_ERR_UNSUPPORTED, "all plans of a batched launch must share the storage type");
     if (plans[i]->iq)
       return fail(DAS_ERR_UNSUPPORTED, "complex baseband plans run through das_forward only");
+    if (plans[i]->interp != DAS_INTERP_LINEAR)
+      return fail(DAS_ERR_UNSUPPORTED, "cubic-interpolation plans run through das_forward only");
   }
   const int algo0 = choose_algo(plans[0], batch[0]);
   for (int i = 0; i < count; ++i) {

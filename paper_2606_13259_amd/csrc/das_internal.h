@@ -142,6 +142,8 @@ hipError_t tiled_forward_bf16(const Geom& g, const TileShape& ts, const Window& 
 hipError_t tiled_forward_fp8(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
                              int B, float* x, hipStream_t st);
 // Complex baseband (IQ pairs), f32 storage.
+hipError_t tiled_forward_f32_cubic(const Geom& g, const TileShape& ts, const Window& w,
+                                   const void* ws, int B, float* x, hipStream_t st);
 hipError_t tiled_forward_f32_iq(const Geom& g, const TileShape& ts, const Window& w, const void* ws,
                                 int B, float* x, hipStream_t st);
 size_t tiled_lds_f32(const Geom& g, int bt, const Window& w);

@@ -256,7 +256,12 @@ __device__ inline void stage_store4(const Stage<1, QN, MC>& st, float* win, int 
 // RUNTIME_VEC: the one-item staging path is chosen per plan at run time (the
 // persistent kernel, whose one-item-per-thread body may serve plans of
 // several items); otherwise BT == 1 implies a one-item plan.
-template <class T, int BT, int QN, bool WTX, bool IQ = false, bool RUNTIME_VEC = false>
+// CUBIC: four-point Lagrange interpolation through samples k-1 .. k+2 instead
+// of the linear interpolation of Eq. (2) (the paper allows other schemes); the
+// window of a tile already holds those taps (tap i = floor(f) + dint lies in
+// [1, 2 dint + 1] and the window has 2 dint + 4 samples).
+template <class T, int BT, int QN, bool WTX, bool IQ = false, bool RUNTIME_VEC = false,
+          bool CUBIC = false>
 __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Window& win,
                                  const T* __restrict__ ws, int B, float* __restrict__ x, int ntx,
                                  int nty, int ntiles, int tile, int b0, unsigned char* smem,
@@ -521,7 +526,9 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           // then the interpolation and accumulation
           auto taps = [&](auto qg_tag, int qa) {
             constexpr int QG = decltype(qg_tag)::value;
+            constexpr int QC = CUBIC ? QG : 1;
             float s1[QG][BT], s2[QG][BT], al[QG], fr[IQ ? QG : 1];
+            float s0[QC][BT], s3[QC][BT];
 #pragma unroll
             for (int r = 0; r < QG; ++r) {
               const float f = a + bq[qa + r];
@@ -532,13 +539,27 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
               for (int b = 0; b < BT; ++b) {
                 s1[r][b] = pp[b];
                 s2[r][b] = pp[QP * BT + b];
+                if constexpr (CUBIC) {
+                  s0[r][b] = pp[b - QP * BT];
+                  s3[r][b] = pp[2 * QP * BT + b];
+                }
               }
             }
             __builtin_amdgcn_sched_barrier(0);  // all reads of the group issue first
 #pragma unroll
             for (int r = 0; r < QG; ++r) {
               const float wt = WTX ? w * wq[WTX ? qa + r : 0] : w;
-              if constexpr (IQ) {
+              if constexpr (CUBIC) {
+                // Lagrange weights of samples k-1, k, k+1, k+2 at k + alpha
+                const float u = al[r], up = u + 1.f, um = u - 1.f, u2 = u - 2.f;
+                const float uum = u * um, upu2 = up * u2;
+                const float cm = uum * u2 * (-1.f / 6.f), c0 = upu2 * um * 0.5f;
+                const float c1 = upu2 * u * -0.5f, c2 = uum * up * (1.f / 6.f);
+#pragma unroll
+                for (int b = 0; b < BT; ++b)
+                  acc[b] = fmaf(wt, fmaf(cm, s0[r][b], fmaf(c0, s1[r][b], fmaf(c1, s2[r][b], c2 * s3[r][b]))),
+                                acc[b]);
+              } else if constexpr (IQ) {
                 // remodulate by exp(i 2 pi fc tau): revolutions fc/fs (ktx + krx
                 // + f) + fc t0, reduced to [0, 1) before the hardware sine and
                 // cosine (which take revolutions)
@@ -619,6 +640,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ti
                                   ktx_s, txl_s);
 }
 
+// Four-point Lagrange (cubic) interpolation variant (the same tile schedule
+// and windows as tiled_forward).
+template <class T, int BT, int QN, bool WTX>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void tiled_forward_cubic(
+    Geom g, TileShape ts, Window win, const T* __restrict__ ws, int B, float* __restrict__ x,
+    int ntx, int nty, int ntiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int ktx_s[16];
+  __shared__ int txl_s[72];
+  constexpr int X = 8, C = 16, per = X * C;
+  const int bx = (int)blockIdx.x;
+  const int tile = bx >= (int)gridDim.x / per * per ? bx : bx / per * per + (bx % per % X) * C + (bx % per) / X;
+  tile_body<T, BT, QN, WTX, false, false, true>(g, ts, win, ws, B, x, ntx, nty, ntiles, tile,
+                                                blockIdx.y * BT, smem, ktx_s, txl_s);
+}
+
 // Several forward passes in one persistent launch: in round r, workgroup w
 // processes work item r G + ((w + 104 r) mod G) (G = gridDim.x); item i
 // belongs to the plan p whose range [first[p], first[p+1]) contains it and
@@ -693,6 +730,50 @@ hipError_t launch_iq_t(const Geom& g, const TileShape& ts, const Window& w, cons
   hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, g, ts, w, static_cast<const T*>(ws), B, x, ntx,
                      nty, ntiles);
   return hipGetLastError();
+}
+
+template <class T, int BT, int QN, bool WTX>
+hipError_t launch_cubic_t(const Geom& g, const TileShape& ts, const Window& w, const void* ws, int B,
+                          float* x, hipStream_t st) {
+  const int ntx = (g.n[0] + ts.tx - 1) / ts.tx, nty = (g.n[1] + ts.ty - 1) / ts.ty,
+            ntz = (g.n[2] + ts.tz - 1) / ts.tz;
+  const int ntiles = ntx * nty * ntz;
+  const size_t lds = lds_bytes_t<BT, QN>(w);
+  dim3 grid(ntiles, (B + BT - 1) / BT);
+  auto kern = tiled_forward_cubic<T, BT, QN, WTX>;
+  if (lds > 65536) {
+    hipError_t e =
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, g, ts, w, static_cast<const T*>(ws), B, x, ntx,
+                     nty, ntiles);
+  return hipGetLastError();
+}
+
+// Cubic-interpolation launch: one, two or four items per thread as the
+// linear launch.
+template <class T>
+hipError_t launch_cubic(const Geom& g, const TileShape& ts, const Window& w, const void* ws, int B,
+                        float* x, hipStream_t st) {
+  const bool wtx = g.w_tx != nullptr;
+  auto pick = [&](auto bt_tag) -> hipError_t {
+    constexpr int BT = decltype(bt_tag)::value;
+    switch (group_size(g.Q)) {
+      case 1: return wtx ? launch_cubic_t<T, BT, 1, true>(g, ts, w, ws, B, x, st)
+                         : launch_cubic_t<T, BT, 1, false>(g, ts, w, ws, B, x, st);
+      case 4: return wtx ? launch_cubic_t<T, BT, 4, true>(g, ts, w, ws, B, x, st)
+                         : launch_cubic_t<T, BT, 4, false>(g, ts, w, ws, B, x, st);
+      case 8: return wtx ? launch_cubic_t<T, BT, 8, true>(g, ts, w, ws, B, x, st)
+                         : launch_cubic_t<T, BT, 8, false>(g, ts, w, ws, B, x, st);
+      default: return wtx ? launch_cubic_t<T, BT, 16, true>(g, ts, w, ws, B, x, st)
+                          : launch_cubic_t<T, BT, 16, false>(g, ts, w, ws, B, x, st);
+    }
+  };
+  const int bt = tiled_batch_per_thread(DAS_STORE_F32, B);
+  if (bt == 4) return pick(std::integral_constant<int, 4>());
+  if (bt == 2) return pick(std::integral_constant<int, 2>());
+  return pick(std::integral_constant<int, 1>());
 }
 
 // Complex baseband launch: B even (I, Q pairs), two or four items per thread.

@@ -28,6 +28,7 @@ STORE = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
 APOD_UNIFORM, APOD_HANN = 0, 1
 ALGO = {"auto": 0, "plain": 1, "tiled": 2, "mfma": 3}
 ALGO_NAME = {v: k for k, v in ALGO.items()}
+DAS_INTERP_LINEAR, DAS_INTERP_CUBIC = 0, 1
 
 
 class DasError(RuntimeError):
@@ -100,6 +101,7 @@ def lib():
             "das_tile_shape": [_I, ctypes.POINTER(_I)],
             "das_debug_delays": [_P, _I, _I, _I, _I, _I, _P, _P],
             "das_plan_set_iq": [_P, _I, ctypes.c_double],
+            "das_plan_set_interp": [_P, _I],
             "das_clutter_workspace_bytes": [_I, ctypes.POINTER(ctypes.c_size_t)],
             "das_clutter_filter": [_P, _I, ctypes.c_int64, _I, _I, _P, _P, _P, _P, _P],
             "das_clutter_filter_noalloc": [_P, _I, ctypes.c_int64, _I, _I, _P, _P, _P, _P],
@@ -320,6 +322,12 @@ class Plan:
         """Complex baseband mode: batch items are (I, Q) pairs demodulated at
         fc (Hz); the forward remodulates every term by exp(i 2 pi fc tau)."""
         _check(lib().das_plan_set_iq(self.handle, int(bool(enable)), float(fc)), "das_plan_set_iq")
+
+    def set_interp(self, interp: str):
+        """Sample interpolation: "linear" (Eq. (2)) or "cubic" (four-point
+        Lagrange through samples k-1 .. k+2; windowed algorithm, f32 storage)."""
+        code = {"linear": DAS_INTERP_LINEAR, "cubic": DAS_INTERP_CUBIC}[interp]
+        _check(lib().das_plan_set_interp(self.handle, code), "das_plan_set_interp")
 
     def set_algo(self, algo: str):
         _check(lib().das_plan_set_algo(self.handle, ALGO[algo]), "das_plan_set_algo")
