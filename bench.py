@@ -168,6 +168,13 @@ def main():
                     help="frames per step for the batched form (0 = skip)")
     ap.add_argument("--ensemble", type=int, default=256,
                     help="frames of the Doppler ensemble (motion frames; 0 = skip)")
+    ap.add_argument("--ensemble-data", choices=("motion", "repeat"), default="motion",
+                    help="ensemble frames: simulated motion frames, or the cfg2 frame repeated "
+                         "(profiling runs: the timing does not depend on the values)")
+    ap.add_argument("--ensemble-storage", default="f16,fp8",
+                    help="storage types of the ensemble MFMA forms")
+    ap.add_argument("--no-ensemble-extras", dest="ensemble_extras", action="store_false",
+                    help="skip the persistent mixed launches, the Doppler pipeline and the clutter filter")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="skip timing the adjoint and sound-speed gradient (cfg5)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -264,6 +271,8 @@ def main():
         pf = das.Plan(g, max_batch=B, storage=storage, algo=algo)
         if pf.algo(B) == "tiled":
             pf.set_tile(plan.tile())
+        elif pf.algo(B) == "mfma":
+            pf.autotune(B)
         if w_tx is not None:
             pf.set_tx_weights(w_tx)
         if iq_fc is not None:
@@ -272,6 +281,7 @@ def main():
         f = {"volumes_per_s": round(1000.0 * B / wf, 2), "ms_per_step": round(wf, 4),
              "forward_ms": round(fwf, 4), "prepare_ms": round(prf, 4), "batch": B,
              "storage": storage, "algo": pf.algo(B),
+             "mfma_form": pf.mfma_form() if pf.algo(B) == "mfma" else None,
              "rel_l2": rel(xf[0, idx_t].cpu().numpy()) if check else None}
         if roof == "valu":
             f["roofline"] = valu_roofline(algorithmic_flops(counts, B), fwf)
@@ -406,25 +416,33 @@ def run_ensemble(args, torch, np, das, synth, g, counts, forms, workers):
     dev = torch.device("cuda:0")
     B = args.ensemble
     t0 = time.perf_counter()
-    log(f"simulating {B} motion frames on the GPU")
-    _, ye, _ = synth.cfg4_ensemble(B, device=dev, progress=lambda d, n: log(
-        f"  {d}/{n} frames ({time.perf_counter() - t0:.1f} s)"))
+    if args.ensemble_data == "repeat":
+        _, _, y1 = synth.cfg2_data(device=dev)
+        ye = y1[None].expand(B, -1, -1, -1).contiguous()
+        del y1
+        note = "the cfg2 frame repeated"
+    else:
+        log(f"simulating {B} motion frames on the GPU")
+        _, ye, _ = synth.cfg4_ensemble(B, device=dev, dtype=torch.float32, progress=lambda d, n: log(
+            f"  {d}/{n} frames ({time.perf_counter() - t0:.1f} s)"))
+        note = ("motion ensemble: the 200 targets + 1e4 speckle scatterers moved by a random walk "
+                "N(0, (lambda/40)^2) per axis per frame (seed 5 + frame), simulated in FP32")
     torch.cuda.synchronize()
-    log(f"  simulated in {time.perf_counter() - t0:.1f} s")
-    note = ("motion ensemble: the 200 targets + 1e4 speckle scatterers moved by a random walk "
-            "N(0, (lambda/40)^2) per axis per frame (seed 5 + frame)")
+    log(f"  ensemble ready in {time.perf_counter() - t0:.1f} s")
     check = sorted({0, 1, B // 2, B - 1})
     idx = np.sort(np.random.default_rng(99).choice(g.N, size=2048, replace=False))
     idx_t = torch.from_numpy(idx).to(dev)
     xo = None
     if not args.no_cpu_baseline:
         xo, _ = oracle_sample(oracle, ye[check].cpu().numpy(), g, idx, workers)
-    for st in ("f16", "fp8"):
+    for st in [v for v in args.ensemble_storage.split(",") if v]:
         pf = das.Plan(g, max_batch=B, storage=st)
+        pf.autotune(B)  # MFMA launch form picked by timing
         wf, prf, fwf, xf = time_form(torch, das, pf, ye, max(2, args.steps // 8), 1)
         f = {"volumes_per_s": round(1000.0 * B / wf, 2), "ms_per_step": round(wf, 4),
              "forward_ms": round(fwf, 4), "prepare_ms": round(prf, 4), "batch": B, "storage": st,
-             "algo": pf.algo(B), "per_frame_latency_ms": round(wf, 3), "data": note,
+             "algo": pf.algo(B), "mfma_form": pf.mfma_form(), "per_frame_latency_ms": round(wf, 3),
+             "data": note,
              "roofline": mfma_roofline(counts, B, st, g, fwf)}
         if xo is not None:
             xs = xf[check][:, idx_t].cpu().numpy()
@@ -479,6 +497,9 @@ def run_ensemble(args, torch, np, das, synth, g, counts, forms, workers):
             p.close()
         torch.cuda.empty_cache()
 
+    if not args.ensemble_extras:
+        del ye
+        return
     run_persistent("persistent_ensemble_mixed", "f16")
     run_persistent("persistent_ensemble_mixed_fp8", "fp8")
 
@@ -486,6 +507,7 @@ def run_ensemble(args, torch, np, das, synth, g, counts, forms, workers):
     # rank-truncation clutter filter (3 tissue components removed) and power
     # Doppler over the 256 volumes.
     pf = das.Plan(g, max_batch=B, storage="f16")
+    pf.autotune(B)
     ws = pf.workspace(B)
     xe = torch.empty(B, g.N, dtype=torch.float32, device=dev)
     wsc = torch.empty(das.das_clutter_workspace_bytes(B), dtype=torch.uint8, device=dev)

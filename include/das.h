@@ -144,6 +144,26 @@ das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
  * DAS_ERR_INVALID_ARG otherwise); das_adjoint, das_grad_sound_speed and
  * das_forward_batched refuse IQ plans.  enable = 0 restores real data. */
 das_status das_plan_set_iq(das_plan p, int32_t enable, double fc);
+/* Launch form of the MFMA algorithm (Sec. 3.4, Alg. 3); Sec. 3.2 says tile
+ * sizes should be picked by profiling, and das_autotune does so for MFMA
+ * plans.  DAS_MFMA_COLUMN: one launch, each wavefront a 4 x 4 x 4 voxel column
+ * (four 4 x 4 MFMA row groups stacked in depth).  DAS_MFMA_SLAB: one launch,
+ * each wavefront an 8 x 8 x 1 slab (four groups side by side at one depth,
+ * whose taps share more sample chunks).  DAS_MFMA_PERSISTENT: the persistent
+ * dynamic-scheduling kernel of das_forward_batched with one plan (4 x 4 x 4
+ * columns).  DAS_MFMA_AUTO (default): persistent where it gives the plan the
+ * same batch tiles per wavefront as the plain launch, else COLUMN.  All forms
+ * read the same workspace and agree up to FP32 summation order and the f16
+ * rounding of the interpolation weights (they form delays relative to
+ * different box centres). */
+typedef enum {
+  DAS_MFMA_AUTO = 0,
+  DAS_MFMA_COLUMN = 1,
+  DAS_MFMA_SLAB = 2,
+  DAS_MFMA_PERSISTENT = 3
+} das_mfma_form;
+das_status das_plan_set_mfma_form(das_plan p, int32_t form);
+das_status das_plan_get_mfma_form(das_plan p, int32_t* form);
 /* Interpolation of the channel samples at the fractional index f of Eq. (1):
  * DAS_INTERP_LINEAR (0, the default) is Eq. (2); DAS_INTERP_CUBIC (1) is the
  * four-point Lagrange interpolant through samples k-1 .. k+2 (k = floor(f)),
@@ -231,10 +251,12 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
                                const int32_t* batch, float* const* x, void* stream);
 
 /* Tile shapes picked by measurement, as Sec. 3.2 says they should be chosen
- * ("determined by profiling").  Times the candidate tile shapes of the TILED
- * algorithm for `batch` items on
- * `stream` (using scratch buffers it allocates and frees) and keep the fastest
- * for this plan.  Synchronizes the stream. */
+ * ("determined by profiling").  For a plan whose algorithm for `batch` items
+ * is the windowed one, times the candidate tile shapes; for the MFMA
+ * algorithm, times the launch forms COLUMN, SLAB and PERSISTENT
+ * (das_mfma_form).  Runs on `stream` with
+ * scratch buffers it allocates and frees (a zeroed workspace of `batch`
+ * items), keeps the fastest for this plan and synchronizes the stream. */
 das_status das_autotune(das_plan p, int32_t batch, void* stream);
 /* Tile shape index the plan uses for TILED (see das_tile_shape).  set_tile
  * returns DAS_ERR_UNSUPPORTED, leaving the plan unchanged, for a shape whose
@@ -270,9 +292,9 @@ das_status das_debug_delays(das_plan p, int32_t q, int32_t m0, int32_t m1, int32
  * (k_hi - k_lo) and T - (k_hi - k_lo) at most 64 (DAS_ERR_UNSUPPORTED
  * otherwise; DAS_ERR_INVALID_ARG for bad sizes or NULL pointers).
  * Method: Gram matrix x x^T on the matrix cores (FP32, chunks merged in
- * FP64); parallel cyclic Jacobi eigen-decomposition (T <= 256: FP32 in LDS,
- * eigenvectors refined in FP64 across the cuts; T > 256: FP64 in global
- * memory); per-voxel projection.
+ * FP64); FP64 eigen-decomposition (Householder tridiagonalisation,
+ * multisection for the eigenvalues, inverse iteration for the eigenvectors,
+ * back-transformation); per-voxel projection.
  * Runs on the calling thread's current device. */
 das_status das_clutter_workspace_bytes(int32_t T, size_t* bytes);
 das_status das_clutter_filter(const float* x, int32_t T, int64_t N, int32_t k_lo, int32_t k_hi,
@@ -281,7 +303,7 @@ das_status das_clutter_filter(const float* x, int32_t T, int64_t N, int32_t k_lo
 /* das_clutter_filter for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same computation with its workspace in a buffer the
- * library holds, a static device array of 12.4 MiB per device that lives
+ * library holds, a static device array of 4.6 MiB per device that lives
  * until the process ends.  No allocation of any kind is made.  Arguments as
  * for das_clutter_filter without ws; T <= 256 (DAS_ERR_INVALID_ARG above).
  * Every call on a device shares that device's buffer: calls that overlap on

@@ -147,6 +147,7 @@ struct das_plan_s {
   bool iq = false;
   double fc = 0.0;
   int interp = DAS_INTERP_LINEAR;  // das_plan_set_interp
+  int mfma_form = DAS_MFMA_AUTO;  // das_plan_set_mfma_form
 };
 
 namespace {
@@ -449,6 +450,21 @@ das_status das_plan_set_algo(das_plan p, int32_t algo) {
   return DAS_OK;
 }
 
+das_status das_plan_set_mfma_form(das_plan p, int32_t form) {
+  if (das_status s = check_plan(p)) return s;
+  if (form < DAS_MFMA_AUTO || form > DAS_MFMA_PERSISTENT)
+    return fail(DAS_ERR_INVALID_ARG, "unknown MFMA form");
+  p->mfma_form = form;
+  return DAS_OK;
+}
+
+das_status das_plan_get_mfma_form(das_plan p, int32_t* form) {
+  if (das_status s = check_plan(p)) return s;
+  if (!form) return fail(DAS_ERR_INVALID_ARG, "form is NULL");
+  *form = p->mfma_form;
+  return DAS_OK;
+}
+
 das_status das_plan_set_interp(das_plan p, int32_t interp) {
   if (das_status s = check_plan(p)) return s;
   if (interp != DAS_INTERP_LINEAR && interp != DAS_INTERP_CUBIC)
@@ -554,11 +570,12 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
     if (!tiled_fits(p, p->tile, batch))
       return fail(DAS_ERR_UNSUPPORTED, "tile windows do not fit in LDS for this geometry");
     e = launch_windowed(p, g, p->tile, ws, batch, x, st);
-  } else if (mfma_prefers_persistent(p->cfg.storage, batch)) {
+  } else if (p->mfma_form == DAS_MFMA_PERSISTENT ||
+             (p->mfma_form == DAS_MFMA_AUTO && mfma_prefers_persistent(p->cfg.storage, batch))) {
     // the persistent kernel with one plan: same results, dynamic balance
     return forward_batched_mfma(1, &p, &ws, &batch, &x, stream);
   } else {
-    e = launch_mfma_forward(g, p->cfg.storage, ws, batch, x, st);
+    e = launch_mfma_forward(g, p->cfg.storage, ws, batch, x, p->mfma_form == DAS_MFMA_SLAB, st);
   }
   if (e != hipSuccess) return hip_fail(e, "das_forward launch");
   return DAS_OK;
@@ -691,12 +708,53 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
   return DAS_OK;
 }
 
+// MFMA plans: time each MFMA launch form on a zeroed workspace of `batch`
+// items (the time does not depend on the sample values) and keep the fastest.
+static das_status autotune_mfma(das_plan p, int32_t batch, hipStream_t st) {
+  const size_t wsb = ws_bytes(p, batch);
+  void* ws = nullptr;
+  float* x = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&ws, wsb);
+  if (e == hipSuccess) e = hipMalloc((void**)&x, sizeof(float) * (size_t)batch * p->N);
+  if (e == hipSuccess) e = hipMemsetAsync(ws, 0, wsb, st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const int saved = p->mfma_form;
+  int best = -1;
+  float best_ms = 1e30f;
+  das_status ds = DAS_OK;
+  const int forms[3] = {DAS_MFMA_COLUMN, DAS_MFMA_SLAB, DAS_MFMA_PERSISTENT};
+  for (int fi = 0; fi < 3 && e == hipSuccess && ds == DAS_OK; ++fi) {
+    p->mfma_form = forms[fi];
+    ds = das_forward(p, ws, batch, x, st);  // warm-up
+    if (ds == DAS_OK) e = hipEventRecord(e0, st);
+    for (int r = 0; r < 2 && e == hipSuccess && ds == DAS_OK; ++r) ds = das_forward(p, ws, batch, x, st);
+    if (ds == DAS_OK && e == hipSuccess) e = hipEventRecord(e1, st);
+    if (ds == DAS_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (ds == DAS_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (ds == DAS_OK && e == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = forms[fi];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (ws) (void)hipFree(ws);
+  if (x) (void)hipFree(x);
+  p->mfma_form = best >= 0 ? best : saved;
+  if (e != hipSuccess) return hip_fail(e, "das_autotune");
+  return ds;
+}
+
 das_status das_autotune(das_plan p, int32_t batch, void* stream) {
   if (das_status s = check_plan(p)) return s;
   if (das_status s = check_batch(p, batch)) return s;
   if (p->iq && batch % 2) return fail(DAS_ERR_INVALID_ARG, "complex baseband needs an even batch");
   DeviceGuard dg(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (choose_algo(p, batch) == DAS_ALGO_MFMA) return autotune_mfma(p, batch, st);
   const int saved_algo = p->algo;
   p->algo = DAS_ALGO_TILED;
   const size_t wsb = ws_bytes(p, batch);

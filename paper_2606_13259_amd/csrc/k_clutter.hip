@@ -12,14 +12,13 @@
 //      FP64 with atomics.  Workgroups own a 64 x 64 block of G (upper
 //      triangle only) for one voxel chunk; the two 64-frame row panels of a
 //      64-voxel step are staged through LDS with coalesced loads.
-//   2. Eigen-decomposition G = V diag(lambda) V^T by the parallel cyclic
-//      Jacobi method (round-robin pairing, T/2 disjoint rotations per round)
-//      in one workgroup.  T <= 256: the matrix lives in that CU's LDS (upper
-//      triangle, FP32), the rotations are logged and replayed on the rows of
-//      V afterwards (FP64); T > 256: matrix and V in global memory (FP64,
-//      much slower: every round waits on L2).  sigma = sqrt(lambda), sorted;
-//      the columns of V that the filter needs are copied (FP32) as the
-//      projection basis B.
+//   2. Eigen-decomposition G = V diag(lambda) V^T in FP64: Householder
+//      tridiagonalisation (one workgroup, matrix in L2), all eigenvalues by
+//      multisection on Sturm counts (one wavefront each), eigenvectors by
+//      inverse iteration (one thread each) re-orthogonalised within
+//      clusters, back-transformed by the reflectors (one workgroup each).
+//      sigma = sqrt(lambda), sorted; the columns of V that the filter needs
+//      are copied (FP32) as the projection basis B.
 //   3. Projection and power: per voxel, a = B^T s_n, then the filtered
 //      series is B a (keep form) or s_n - B a (removal form), whichever uses
 //      fewer components (at most 64), and P[n] its mean square.  Every voxel
@@ -109,386 +108,334 @@ __device__ inline double& up(double* a, int T, int i, int j) {
   return i <= j ? a[(size_t)i * T + j] : a[(size_t)j * T + i];
 }
 
-// Parallel cyclic Jacobi on the T x T symmetric matrix a (upper triangle,
-// overwritten: its diagonal ends as the eigenvalues) with eigenvectors
-// accumulated in v (T x T, columns).  One workgroup of 1024 threads.
-// Round r pairs the indices by the round-robin (circle) schedule over
-// Tp = T rounded up to even (index T, if present, is a dummy that never
-// rotates).  Per round: the T/2 rotations are formed (each pair also updates
-// its own 2 x 2 diagonal block in closed form), then every off-diagonal 2 x 2
-// block between two pairs becomes R1^T M R2 and the columns p, q of v rotate.
-// Sweeps stop when the off-diagonal mass falls below 1e-26 of the diagonal
-// mass (squares), or after 40 sweeps.  Then the eigenvalues are ranked
-// (descending, ties by index), sigma = sqrt(max(lambda, 0)) is written, and
-// the basis columns (ranks [k_lo, k_hi) for keep, the others for removal) are
-// copied to B[T][nb] in FP32.
-__global__ __launch_bounds__(1024) void jacobi_eig(double* __restrict__ a, double* __restrict__ v,
-                                                   int T, int k_lo, int k_hi, int keep,
-                                                   float* __restrict__ sv, float* __restrict__ Bm,
-                                                   int nb) {
-  constexpr int MAXP = 256;  // pairs (T <= 512)
-  __shared__ int P[MAXP], Q[MAXP];
-  __shared__ double C[MAXP], S[MAXP];
-  __shared__ double red[2][32];
-  __shared__ int rank_of[512];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int Tp = T + (T & 1), np = Tp / 2;
-  for (int i = tid; i < T * T; i += nt) v[i] = (i / T == i % T) ? 1.0 : 0.0;
+constexpr int kMaxT = 512;
+
+// Block-wide FP64 sum over blockDim.x threads (a multiple of 64, at most
+// 1024); every thread returns the total.  red: 16 doubles of LDS.
+__device__ inline double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int nw = blockDim.x >> 6;
+  __syncthreads();  // red is free (a previous call has been read)
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    for (int r = 0; r < Tp - 1; ++r) {
-      if (tid < np) {
-        auto pos = [&](int k) { return k == 0 ? 0 : 1 + (k - 1 + r) % (Tp - 1); };
-        int p = pos(tid), q = pos(Tp - 1 - tid);
-        if (p > q) {
-          const int w = p;
-          p = q;
-          q = w;
-        }
-        double c = 1.0, s = 0.0;
-        if (q < T) {
-          const double app = up(a, T, p, p), aqq = up(a, T, q, q), apq = up(a, T, p, q);
-          if (apq != 0.0) {
-            const double th = (aqq - app) / (2.0 * apq);
-            const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(tt * tt + 1.0);
-            s = tt * c;
-            up(a, T, p, p) = app - tt * apq;
-            up(a, T, q, q) = aqq + tt * apq;
-            up(a, T, p, q) = 0.0;
-          }
-        }
-        P[tid] = p;
-        Q[tid] = q;
-        C[tid] = c;
-        S[tid] = s;
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += red[w];
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Eigen-decomposition of the FP64 Gram matrix G (T x T, T <= 512) in four
+// steps, all in FP64:
+//   1. Householder reduction to tridiagonal form, Q^T G Q = tridiag(e, d, e),
+//      Q = H_0 H_1 ... H_{T-3}, H_k = I - tau_k u_k u_k^T (one workgroup; the
+//      working matrix lives in global memory and stays in L2);
+//   2. every eigenvalue of the tridiagonal matrix by multisection on Sturm
+//      counts (one wavefront per eigenvalue, 64 points per iteration);
+//   3. its eigenvectors by inverse iteration (one thread per vector, LU with
+//      partial pivoting of the shifted tridiagonal matrix), re-orthogonalised
+//      within clusters of (nearly) equal eigenvalues;
+//   4. back-transformation V = Q Y (one workgroup per vector).
+// FP64 keeps every eigenvector accurate to ~1e-16 of the largest eigenvalue
+// over its gap, also for the weak components of a wide dynamic range.
+
+// 1. A: working copy of G (full, row-major); on return the Householder vector
+// u_k (its entries k+1 .. T-1, the first scaled to u_k[k+1]) sits in column k
+// below the diagonal.
+__global__ __launch_bounds__(1024) void tri_reduce(const double* __restrict__ G, int T,
+                                                   double* __restrict__ A, double* __restrict__ d,
+                                                   double* __restrict__ e, double* __restrict__ tau) {
+  __shared__ double v[kMaxT], w[kMaxT], red[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int i = tid; i < T * T; i += blockDim.x) A[i] = G[i];
+  __syncthreads();
+  for (int k = 0; k + 2 < T; ++k) {
+    const int n = T - k - 1;  // the trailing block is rows / columns k+1 .. T-1
+    const double xi = tid < n ? A[(size_t)(k + 1 + tid) * T + k] : 0.0;
+    const double ss = block_sum(xi * xi, red);
+    const double x0 = A[(size_t)(k + 1) * T + k];
+    const double tail = ss - x0 * x0;
+    if (tail <= 1e-300 * fmax(ss, 1e-300) || ss == 0.0) {
+      // column already reduced: H_k = I
+      if (tid == 0) {
+        d[k] = A[(size_t)k * T + k];
+        e[k] = x0;
+        tau[k] = 0.0;
       }
       __syncthreads();
-      // off-diagonal blocks between pairs k1 < k2
-      const int nblk = np * (np - 1) / 2;
-      for (int w = tid; w < nblk; w += nt) {
-        int k2 = (int)((1.0 + sqrt(1.0 + 8.0 * (double)w)) * 0.5);
-        while (k2 * (k2 - 1) / 2 > w) --k2;
-        while ((k2 + 1) * k2 / 2 <= w) ++k2;
-        const int k1 = w - k2 * (k2 - 1) / 2;
-        const int p1 = P[k1], q1 = Q[k1], p2 = P[k2], q2 = Q[k2];
-        const double c1 = C[k1], s1 = S[k1], c2 = C[k2], s2 = S[k2];
-        if ((s1 == 0.0 && s2 == 0.0) || p1 >= T || p2 >= T) continue;
-        const bool q1v = q1 < T, q2v = q2 < T;
-        const double m00 = up(a, T, p1, p2);
-        const double m01 = q2v ? up(a, T, p1, q2) : 0.0;
-        const double m10 = q1v ? up(a, T, q1, p2) : 0.0;
-        const double m11 = (q1v && q2v) ? up(a, T, q1, q2) : 0.0;
-        // rows (p1, q1) by R1, then columns (p2, q2) by R2
-        const double b00 = c1 * m00 - s1 * m10, b01 = c1 * m01 - s1 * m11;
-        const double b10 = s1 * m00 + c1 * m10, b11 = s1 * m01 + c1 * m11;
-        up(a, T, p1, p2) = c2 * b00 - s2 * b01;
-        if (q2v) up(a, T, p1, q2) = s2 * b00 + c2 * b01;
-        if (q1v) up(a, T, q1, p2) = c2 * b10 - s2 * b11;
-        if (q1v && q2v) up(a, T, q1, q2) = s2 * b10 + c2 * b11;
-      }
-      // eigenvector columns
-      for (int w = tid; w < np * T; w += nt) {
-        const int k = w / T, i = w - k * T;
-        const int p = P[k], q = Q[k];
-        const double c = C[k], s = S[k];
-        if (s == 0.0 || q >= T) continue;
-        const double vp = v[(size_t)i * T + p], vq = v[(size_t)i * T + q];
-        v[(size_t)i * T + p] = c * vp - s * vq;
-        v[(size_t)i * T + q] = s * vp + c * vq;
-      }
-      __syncthreads();
+      continue;
     }
-    // convergence: off-diagonal vs diagonal mass
-    double off = 0.0, dia = 0.0;
-    for (int w = tid; w < T * T; w += nt) {
-      const int i = w / T, j = w - i * T;
-      const double e = a[w];
-      if (i < j) off += e * e;
-      if (i == j) dia += e * e;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      off += __shfl_xor(off, o);
-      dia += __shfl_xor(dia, o);
-    }
-    if ((tid & 63) == 0) {
-      red[0][tid >> 6] = off;
-      red[1][tid >> 6] = dia;
+    const double alpha = x0 >= 0.0 ? -sqrt(ss) : sqrt(ss);
+    const double t = 1.0 / (alpha * (alpha - x0));  // 2 / (u^T u)
+    if (tid < n) v[tid] = tid == 0 ? x0 - alpha : xi;
+    __syncthreads();
+    // p = t B u (rows by wavefronts, columns by lanes), w = p - (t/2 u^T p) u
+    for (int i = wave; i < n; i += nw) {
+      const double* row = A + (size_t)(k + 1 + i) * T + (k + 1);
+      double acc = 0.0;
+      for (int j = lane; j < n; j += 64) acc += row[j] * v[j];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (lane == 0) w[i] = t * acc;
     }
     __syncthreads();
-    off = 0.0;
-    dia = 0.0;
-    for (int w = 0; w < nt / 64; ++w) {
-      off += red[0][w];
-      dia += red[1][w];
-    }
+    const double up_ = block_sum(tid < n ? v[tid] * w[tid] : 0.0, red);
+    const double K = 0.5 * t * up_;
+    if (tid < n) w[tid] -= K * v[tid];
     __syncthreads();
-    if (off <= 1e-26 * dia) break;  // uniform: every thread read the same sums
+    // B -= u w^T + w u^T
+    for (int i = wave; i < n; i += nw) {
+      double* row = A + (size_t)(k + 1 + i) * T + (k + 1);
+      const double vi = v[i], wi = w[i];
+      for (int j = lane; j < n; j += 64) row[j] -= vi * w[j] + wi * v[j];
+    }
+    if (tid == 0) {
+      d[k] = A[(size_t)k * T + k];
+      e[k] = alpha;
+      tau[k] = t;
+    }
+    if (tid < n) A[(size_t)(k + 1 + tid) * T + k] = v[tid];
+    __syncthreads();
   }
-  // rank the eigenvalues, descending (ties by index)
+  if (tid == 0) {
+    if (T >= 2) {
+      d[T - 2] = A[(size_t)(T - 2) * T + T - 2];
+      e[T - 2] = A[(size_t)(T - 1) * T + T - 2];
+      tau[T - 2] = 0.0;
+    }
+    d[T - 1] = A[(size_t)(T - 1) * T + T - 1];
+    if (T >= 1) tau[T - 1] = 0.0;
+  }
+}
+
+// Number of eigenvalues of tridiag(e, d, e) below x (Sturm sequence of the
+// LDL^T factorisation of T - x I; zero pivots replaced by -pivmin).
+__device__ inline int sturm_count(const double* d, const double* e2, int T, double x, double pivmin) {
+  double q = d[0] - x;
+  int c = q < 0.0;
+  for (int t = 1; t < T; ++t) {
+    if (fabs(q) < pivmin) q = -pivmin;
+    q = d[t] - x - e2[t - 1] / q;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+// 2. Eigenvalue i (ascending) in wavefront i: 64 points per iteration, the
+// bracket shrinks 65-fold each time; Gershgorin bounds to start.
+__global__ __launch_bounds__(64) void tri_bisect(const double* __restrict__ d,
+                                                 const double* __restrict__ e, int T,
+                                                 double* __restrict__ lam) {
+  __shared__ double sd[kMaxT], se2[kMaxT];
+  const int lane = threadIdx.x, i = blockIdx.x;
+  double lo = 1e300, hi = -1e300, emax = 0.0;
+  for (int t = lane; t < T; t += 64) {
+    const double el = t > 0 ? fabs(e[t - 1]) : 0.0, er = t + 1 < T ? fabs(e[t]) : 0.0;
+    sd[t] = d[t];
+    se2[t] = er * er;
+    lo = fmin(lo, d[t] - el - er);
+    hi = fmax(hi, d[t] + el + er);
+    emax = fmax(emax, er);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+    emax = fmax(emax, __shfl_xor(emax, o));
+  }
+  __syncthreads();
+  const double scale = fmax(fabs(lo), fabs(hi));
+  const double pivmin = fmax(1e-290, 1e-300 * emax * emax);
+  lo -= 1e-14 * scale + 1e-300;
+  hi += 1e-14 * scale + 1e-300;
+  for (int it = 0; it < 12 && hi - lo > 2e-16 * fmax(fabs(lo), fabs(hi)); ++it) {
+    const double h = (hi - lo) / 65.0;
+    const double x = lo + (lane + 1) * h;
+    const int c = sturm_count(sd, se2, T, x, pivmin);
+    // first point with more than i eigenvalues below it
+    const uint64_t above = __ballot(c > i);
+    const int j = above ? __builtin_ctzll(above) : 64;
+    const double nlo = lo + j * h, nhi = j < 64 ? lo + (j + 1) * h : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) lam[i] = 0.5 * (lo + hi);
+}
+
+// 3. Inverse iteration, one thread per eigenvector j: Gaussian elimination
+// with partial pivoting of tridiag(e, d - lam_j, e) (U with two
+// superdiagonals, multipliers and row-swap flags in sc[5][T][T], component-
+// major so that the threads of a wavefront touch consecutive addresses),
+// then three solves from a fixed pseudo-random start, each normalised.
+// Y[t][j] = component t of eigenvector j.
+__global__ __launch_bounds__(64) void tri_inverse(const double* __restrict__ d,
+                                                  const double* __restrict__ e,
+                                                  const double* __restrict__ lam, int T,
+                                                  double* __restrict__ sc, double* __restrict__ Y) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= T) return;
+  const size_t TT = (size_t)T * T;
+  double* U0 = sc;
+  double* U1 = sc + TT;
+  double* U2 = sc + 2 * TT;
+  double* L = sc + 3 * TT;
+  double* P = sc + 4 * TT;
+  auto at = [&](double* arr, int t) -> double& { return arr[(size_t)t * T + j]; };
+  double anorm = 0.0;
+  for (int t = 0; t < T; ++t)
+    anorm = fmax(anorm, fabs(d[t]) + (t > 0 ? fabs(e[t - 1]) : 0.0) + (t + 1 < T ? fabs(e[t]) : 0.0));
+  const double tiny = fmax(1e-280, 2.2e-16 * anorm);
+  const double lj = lam[j];
+  // the current row has entries (a, b) at (x_t, x_{t+1}); the next original
+  // row is (e_t, d_{t+1} - lam, e_{t+1}) at (x_t, x_{t+1}, x_{t+2})
+  double a = d[0] - lj, b = T > 1 ? e[0] : 0.0;
+  for (int t = 0; t + 1 < T; ++t) {
+    const double sub = e[t], na = d[t + 1] - lj, nb = t + 2 < T ? e[t + 1] : 0.0;
+    if (fabs(sub) > fabs(a)) {  // swap: the next row is the pivot row
+      const double m = a / sub;
+      at(U0, t) = sub;
+      at(U1, t) = na;
+      at(U2, t) = nb;
+      at(L, t) = m;
+      at(P, t) = 1.0;
+      a = b - m * na;
+      b = -m * nb;
+    } else {
+      if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
+      const double m = sub / a;
+      at(U0, t) = a;
+      at(U1, t) = b;
+      at(U2, t) = 0.0;
+      at(L, t) = m;
+      at(P, t) = 0.0;
+      a = na - m * b;
+      b = nb;
+    }
+  }
+  if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
+  at(U0, T - 1) = a;
+  at(U1, T - 1) = 0.0;
+  at(U2, T - 1) = 0.0;
+  // start vector
+  for (int t = 0; t < T; ++t) {
+    const uint32_t h = (uint32_t)t * 2654435761u ^ ((uint32_t)j * 40503u + 0x9e3779b9u);
+    at(Y, t) = 0.5 + (double)((h >> 8) & 0xffff) / 65536.0;
+  }
+  for (int it = 0; it < 3; ++it) {
+    // forward: apply the row operations to the right-hand side (in place)
+    double r = at(Y, 0);
+    for (int t = 0; t + 1 < T; ++t) {
+      const double y1 = at(Y, t + 1), m = at(L, t);
+      if (at(P, t) != 0.0) {
+        at(Y, t) = y1;
+        r = r - m * y1;
+      } else {
+        at(Y, t) = r;
+        r = y1 - m * r;
+      }
+    }
+    at(Y, T - 1) = r;
+    // back substitution
+    double x2 = 0.0, x1 = at(Y, T - 1) / at(U0, T - 1);
+    at(Y, T - 1) = x1;
+    double nrm = x1 * x1;
+    for (int t = T - 2; t >= 0; --t) {
+      const double x = (at(Y, t) - at(U1, t) * x1 - at(U2, t) * x2) / at(U0, t);
+      at(Y, t) = x;
+      nrm += x * x;
+      x2 = x1;
+      x1 = x;
+    }
+    const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+    for (int t = 0; t < T; ++t) at(Y, t) *= inv;
+  }
+}
+
+// 3b. Re-orthogonalise eigenvectors within clusters of eigenvalues closer
+// than 1e-9 of the spectral radius (inverse iteration leaves vectors of
+// (nearly) equal eigenvalues non-orthogonal), by classical Gram-Schmidt
+// applied twice, in ascending order; one workgroup.
+__global__ __launch_bounds__(1024) void tri_orth(const double* __restrict__ lam, int T,
+                                                 double* __restrict__ Y) {
+  __shared__ double dots[kMaxT], red[16];
+  const int tid = threadIdx.x;
+  double lmax = 0.0;
+  for (int j = 0; j < T; ++j) lmax = fmax(lmax, fabs(lam[j]));
+  const double tol = 1e-9 * lmax;
+  int cs = 0;  // first vector of the current cluster
+  for (int j = 1; j < T; ++j) {
+    if (lam[j] - lam[j - 1] > tol) {
+      cs = j;
+      continue;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      // dots with the cluster's previous vectors (one thread each)
+      for (int i = cs + tid; i < j; i += blockDim.x) {
+        double acc = 0.0;
+        for (int t = 0; t < T; ++t) acc += Y[(size_t)t * T + i] * Y[(size_t)t * T + j];
+        dots[i] = acc;
+      }
+      __syncthreads();
+      for (int t = tid; t < T; t += blockDim.x) {
+        double y = Y[(size_t)t * T + j];
+        for (int i = cs; i < j; ++i) y -= dots[i] * Y[(size_t)t * T + i];
+        Y[(size_t)t * T + j] = y;
+      }
+      __syncthreads();
+    }
+    double part = 0.0;
+    for (int t = tid; t < T; t += blockDim.x) part += Y[(size_t)t * T + j] * Y[(size_t)t * T + j];
+    const double nrm = block_sum(part, red);
+    const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+    for (int t = tid; t < T; t += blockDim.x) Y[(size_t)t * T + j] *= inv;
+    __syncthreads();
+  }
+}
+
+// 4. V = Q Y, one workgroup per eigenvector j: the Householder reflectors
+// H_{T-3} .. H_0 applied in turn.
+__global__ __launch_bounds__(256) void tri_back(const double* __restrict__ A,
+                                                const double* __restrict__ tau,
+                                                const double* __restrict__ Y,
+                                                int T, double* __restrict__ V) {
+  __shared__ double y[kMaxT], red[16];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  for (int t = tid; t < T; t += blockDim.x) y[t] = Y[(size_t)t * T + j];
+  __syncthreads();
+  for (int k = T - 3; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;  // uniform
+    const int n = T - k - 1;
+    double part = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) part += A[(size_t)(k + 1 + i) * T + k] * y[k + 1 + i];
+    const double s = tk * block_sum(part, red);
+    for (int i = tid; i < n; i += blockDim.x) y[k + 1 + i] -= s * A[(size_t)(k + 1 + i) * T + k];
+    __syncthreads();
+  }
+  for (int t = tid; t < T; t += blockDim.x) V[(size_t)t * T + j] = y[t];
+}
+
+// Rank the eigenvalues (descending, ties by index), write sigma = sqrt(lambda),
+// and copy the projection basis B[T][nb] (FP32): the eigenvectors of ranks
+// [k_lo, k_hi) for the keep form, the others for the removal form.
+__global__ __launch_bounds__(1024) void rank_basis(const double* __restrict__ lam,
+                                                   const double* __restrict__ v, int T, int k_lo,
+                                                   int k_hi, int keep, float* __restrict__ sv,
+                                                   float* __restrict__ Bm, int nb) {
+  __shared__ int rank_of[kMaxT];
+  const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < T; i += nt) {
-    const double li = a[(size_t)i * T + i];
+    const double li = lam[i];
     int rk = 0;
     for (int j = 0; j < T; ++j) {
-      const double lj = a[(size_t)j * T + j];
+      const double lj = lam[j];
       rk += (lj > li) || (lj == li && j < i);
     }
     rank_of[rk] = i;
     sv[rk] = (float)sqrt(fmax(li, 0.0));
   }
   __syncthreads();
-  // basis columns: ranks in [k_lo, k_hi) (keep) or outside it (removal)
   for (int w = tid; w < T * nb; w += nt) {
     const int t = w / nb, j = w - t * nb;
     const int rk = keep ? k_lo + j : (j < k_lo ? j : k_hi + (j - k_lo));
     Bm[w] = (float)v[(size_t)t * T + rank_of[rk]];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Fast path for T <= 256: the same parallel Jacobi with the matrix in LDS.
-// The upper triangle in FP32 (T (T+1)/2 floats, at most 128.5 KiB) stays in
-// one CU's LDS for all sweeps; every rotation (c, s, p, q) is logged to
-// global memory and the eigenvectors are formed afterwards by replaying the
-// log on the rows of V (rows evolve independently: row i only ever mixes its
-// own entries p and q), in FP64, one row per thread.  FP32 is ample here:
-// the eigenvalues are needed to a small fraction of sigma_1^2 and the
-// eigenvectors only across the gaps at the cuts.
-constexpr int kFastT = 256;
-constexpr int kMaxSweeps = 30;
-
-struct Rot {
-  float c, s;
-  short p, q;
-};
-
-__device__ inline int upk(int T, int i, int j) {  // packed upper-triangle index, i <= j
-  return i * T - (i * (i - 1)) / 2 + (j - i);
-}
-__device__ inline float& upl(float* a, int T, int i, int j) {
-  return i <= j ? a[upk(T, i, j)] : a[upk(T, j, i)];
-}
-
-__global__ __launch_bounds__(1024) void jacobi_lds(const double* __restrict__ G, int T,
-                                                   Rot* __restrict__ log, int* __restrict__ nrot,
-                                                   float* __restrict__ lam) {
-  extern __shared__ float A[];  // T (T+1)/2
-  __shared__ int P[kFastT / 2], Q[kFastT / 2];
-  __shared__ float C[kFastT / 2], S[kFastT / 2];
-  __shared__ float red[2][16];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int Tp = T + (T & 1), np = Tp / 2;
-  for (int w = tid; w < T * T; w += nt) {
-    const int i = w / T, j = w - i * T;
-    if (i <= j) A[upk(T, i, j)] = (float)G[w];
-  }
-  __syncthreads();
-  __shared__ int rotated;
-  if (tid == 0) rotated = 0;
-  __syncthreads();
-  int sweeps = 0;
-  for (; sweeps < kMaxSweeps; ++sweeps) {
-    for (int r = 0; r < Tp - 1; ++r) {
-      if (tid < np) {
-        auto pos = [&](int k) { return k == 0 ? 0 : 1 + (k - 1 + r) % (Tp - 1); };
-        int p = pos(tid), q = pos(Tp - 1 - tid);
-        if (p > q) {
-          const int w = p;
-          p = q;
-          q = w;
-        }
-        float c = 1.f, s = 0.f;
-        if (q < T) {
-          const float app = upl(A, T, p, p), aqq = upl(A, T, q, q), apq = upl(A, T, p, q);
-          if (fabsf(apq) > 1.1920929e-7f * sqrtf(fabsf(app * aqq))) {
-            rotated = 1;
-            const float th = (aqq - app) / (2.f * apq);
-            const float tt = (th >= 0.f ? 1.f : -1.f) / (fabsf(th) + sqrtf(th * th + 1.f));
-            c = 1.f / sqrtf(tt * tt + 1.f);
-            s = tt * c;
-            upl(A, T, p, p) = app - tt * apq;
-            upl(A, T, q, q) = aqq + tt * apq;
-            upl(A, T, p, q) = 0.f;
-          }
-        }
-        P[tid] = p;
-        Q[tid] = q;
-        C[tid] = c;
-        S[tid] = s;
-        log[((size_t)sweeps * (Tp - 1) + r) * np + tid] = Rot{c, s, (short)p, (short)q};
-      }
-      __syncthreads();
-      const int nblk = np * (np - 1) / 2;
-      for (int w = tid; w < nblk; w += nt) {
-        int k2 = (int)((1.f + sqrtf(1.f + 8.f * (float)w)) * 0.5f);
-        while (k2 * (k2 - 1) / 2 > w) --k2;
-        while ((k2 + 1) * k2 / 2 <= w) ++k2;
-        const int k1 = w - k2 * (k2 - 1) / 2;
-        const float s1 = S[k1], s2 = S[k2];
-        if (s1 == 0.f && s2 == 0.f) continue;
-        const int p1 = P[k1], q1 = Q[k1], p2 = P[k2], q2 = Q[k2];
-        const float c1 = C[k1], c2 = C[k2];
-        const bool q1v = q1 < T, q2v = q2 < T;
-        const float m00 = upl(A, T, p1, p2);
-        const float m01 = q2v ? upl(A, T, p1, q2) : 0.f;
-        const float m10 = q1v ? upl(A, T, q1, p2) : 0.f;
-        const float m11 = (q1v && q2v) ? upl(A, T, q1, q2) : 0.f;
-        const float b00 = c1 * m00 - s1 * m10, b01 = c1 * m01 - s1 * m11;
-        const float b10 = s1 * m00 + c1 * m10, b11 = s1 * m01 + c1 * m11;
-        upl(A, T, p1, p2) = c2 * b00 - s2 * b01;
-        if (q2v) upl(A, T, p1, q2) = s2 * b00 + c2 * b01;
-        if (q1v) upl(A, T, q1, p2) = c2 * b10 - s2 * b11;
-        if (q1v && q2v) upl(A, T, q1, q2) = s2 * b10 + c2 * b11;
-      }
-      __syncthreads();
-    }
-    float off = 0.f, dia = 0.f;
-    for (int w = tid; w < T * T; w += nt) {
-      const int i = w / T, j = w - i * T;
-      if (i < j) {
-        const float e = A[upk(T, i, j)];
-        off += e * e;
-      } else if (i == j) {
-        const float e = A[upk(T, i, i)];
-        dia += e * e;
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      off += __shfl_xor(off, o);
-      dia += __shfl_xor(dia, o);
-    }
-    if ((tid & 63) == 0) {
-      red[0][tid >> 6] = off;
-      red[1][tid >> 6] = dia;
-    }
-    __syncthreads();
-    off = 0.f;
-    dia = 0.f;
-    for (int w = 0; w < nt / 64; ++w) {
-      off += red[0][w];
-      dia += red[1][w];
-    }
-    __syncthreads();
-    // converged: off-diagonal mass negligible, or a whole sweep without a
-    // rotation (every |a_pq| <= 2^-23 sqrt(a_pp a_qq): the relative
-    // criterion, which keeps refining the small eigenpairs)
-    const bool none = rotated == 0;
-    __syncthreads();
-    if (off <= 1e-13f * dia || none) {
-      ++sweeps;
-      break;
-    }
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-  }
-  for (int i = tid; i < T; i += nt) lam[i] = A[upk(T, i, i)];
-  if (tid == 0) *nrot = sweeps * (Tp - 1) * np;
-}
-
-// V = product of the logged rotations, row by row: row i starts as e_i and
-// every rotation (c, s, p, q) mixes its entries p and q.  Rows are
-// independent, and the rotations of one round touch disjoint entries, so one
-// wavefront replays one row with its lanes sharing each round's rotations
-// (lane l takes pairs l, l + 64, ...); the rounds run in program order on the
-// row held in LDS (one wavefront: LDS operations stay in order, no barrier).
-__global__ __launch_bounds__(64) void replay_rotations(const Rot* __restrict__ log,
-                                                       const int* __restrict__ nrot, int T,
-                                                       double* __restrict__ v) {
-  __shared__ double row[kFastT];
-  const int lane = threadIdx.x, i = blockIdx.x;
-  const int np = (T + (T & 1)) / 2;
-  for (int j = lane; j < T; j += 64) row[j] = (j == i) ? 1.0 : 0.0;
-  __builtin_amdgcn_wave_barrier();
-  const int nrounds = *nrot / np;
-  for (int k = 0; k < nrounds; ++k) {
-    const Rot* rk = log + (size_t)k * np;
-    for (int j = lane; j < np; j += 64) {
-      const Rot r = rk[j];
-      if (r.s == 0.f || r.q >= T) continue;
-      // renormalised in FP64: FP32 (c, s) have c^2 + s^2 = 1 +- 1e-7, and a
-      // row meets thousands of rotations
-      const double inv = 1.0 / sqrt((double)r.c * r.c + (double)r.s * r.s);
-      const double c = r.c * inv, s = r.s * inv;
-      const double vp = row[r.p], vq = row[r.q];
-      row[r.p] = c * vp - s * vq;
-      row[r.q] = s * vp + c * vq;
-    }
-    __builtin_amdgcn_wave_barrier();  // round k's updates precede round k + 1's reads
-  }
-  for (int j = lane; j < T; j += 64) v[(size_t)i * T + j] = row[j];
-}
-
-// Rank the eigenvalues lam (descending, ties by index), write sigma, and form
-// the projection basis B[T][nb] (ranks [k_lo, k_hi) for keep, the others for
-// removal), refined in FP64 across the cuts.  The FP32 Jacobi leaves each
-// eigenvector accurate to about the FP32 rounding of the matrix; the filter
-// only depends on the split between the basis set D and its complement K, so
-// one first-order correction with the FP64 Gram matrix G removes that error:
-//   W = G V_D,   delta_id = v_i . W_d,   b_d = v_d + sum_{i in K} v_i delta_id / (lam_d - lam_i)
-// (second-order terms, (delta / gap)^2, are far below FP32).  Pairs closer
-// than 1e-6 lam_max are not corrected (no gap: the split is not unique
-// there).  G's storage is reused for the coefficients E once W is formed.
-__global__ __launch_bounds__(1024) void rank_refine_basis(const float* __restrict__ lam,
-                                                          const double* __restrict__ v, double* G,
-                                                          double* __restrict__ W, int T, int k_lo,
-                                                          int k_hi, int keep, float* __restrict__ sv,
-                                                          float* __restrict__ Bm, int nb) {
-  __shared__ int rank_of[kFastT], D[64], Kset[kFastT];
-  __shared__ unsigned char inD[kFastT];
-  __shared__ float lmax;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < T; i += nt) {
-    const float li = lam[i];
-    int rk = 0;
-    for (int j = 0; j < T; ++j) {
-      const float lj = lam[j];
-      rk += (lj > li) || (lj == li && j < i);
-    }
-    rank_of[rk] = i;
-    sv[rk] = sqrtf(fmaxf(li, 0.f));
-    inD[i] = 0;
-  }
-  __syncthreads();
-  if (tid == 0) lmax = fmaxf(lam[rank_of[0]], 0.f);
-  for (int j = tid; j < nb; j += nt) {
-    const int rk = keep ? k_lo + j : (j < k_lo ? j : k_hi + (j - k_lo));
-    D[j] = rank_of[rk];
-  }
-  __syncthreads();
-  for (int j = tid; j < nb; j += nt) inD[D[j]] = 1;
-  __syncthreads();
-  if (tid == 0) {
-    int c = 0;
-    for (int i = 0; i < T; ++i)
-      if (!inD[i]) Kset[c++] = i;
-  }
-  __syncthreads();
-  const int nK = T - nb;
-  // W = G V_D
-  for (int w = tid; w < T * nb; w += nt) {
-    const int t = w / nb, j = w - t * nb;
-    const int d = D[j];
-    double acc = 0.0;
-    for (int u = 0; u < T; ++u) acc += up(G, T, t, u) * v[(size_t)u * T + d];
-    W[w] = acc;
-  }
-  __syncthreads();
-  // E[i][j] (i over K) into G's storage
-  double* E = G;
-  for (int w = tid; w < nK * nb; w += nt) {
-    const int ii = w / nb, j = w - ii * nb;
-    const int i = Kset[ii], d = D[j];
-    double dl = 0.0;
-    for (int t = 0; t < T; ++t) dl += v[(size_t)t * T + i] * W[t * nb + j];
-    const double gap = (double)lam[d] - (double)lam[i];
-    E[w] = fabs(gap) > 1e-6 * (double)lmax ? dl / gap : 0.0;
-  }
-  __syncthreads();
-  for (int w = tid; w < T * nb; w += nt) {
-    const int t = w / nb, j = w - t * nb;
-    double b = v[(size_t)t * T + D[j]];
-    for (int ii = 0; ii < nK; ++ii) b += v[(size_t)t * T + Kset[ii]] * E[ii * nb + j];
-    Bm[w] = (float)b;
   }
 }
 
@@ -545,21 +492,33 @@ hipError_t launch_project(const float* x, int T, long long N, const float* Bm, i
 
 constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-constexpr size_t rot_log_bytes(int T) {
-  const int Tp = T + (T & 1);
-  return align256(sizeof(Rot) * (size_t)kMaxSweeps * (Tp - 1) * (Tp / 2));
+// Workspace layout (bytes from the start), every part 256-byte aligned:
+// G, V, A, Y (T x T f64 each), sc (5 T x T f64: the tridiagonal factors),
+// Bm (T x 64 f32), d, e, tau, lam (T f64 each).
+struct ClutterWs {
+  size_t G, V, A, Y, sc, Bm, d, e, tau, lam, total;
+};
+constexpr ClutterWs ws_layout(int T) {
+  const size_t tt = align256(sizeof(double) * (size_t)T * T), t8 = align256(sizeof(double) * (size_t)T);
+  ClutterWs L{};
+  size_t o = 0;
+  L.G = o; o += tt;
+  L.V = o; o += tt;
+  L.A = o; o += tt;
+  L.Y = o; o += tt;
+  L.sc = o; o += 5 * tt;
+  L.Bm = o; o += align256(sizeof(float) * (size_t)T * 64);
+  L.d = o; o += t8;
+  L.e = o; o += t8;
+  L.tau = o; o += t8;
+  L.lam = o; o += t8;
+  L.total = o;
+  return L;
 }
-
-constexpr size_t workspace_bytes(int T) {
-  size_t b = 2 * align256(sizeof(double) * (size_t)T * T) + align256(sizeof(float) * (size_t)T * 64);
-  if (T <= kFastT)
-    b += rot_log_bytes(T) + align256(sizeof(float) * (size_t)T) + 256 +
-         align256(sizeof(double) * (size_t)T * 64);
-  return b;
-}
+constexpr size_t workspace_bytes(int T) { return ws_layout(T).total; }
 
 // Workspace of the allocation-free entry point: room for ensembles of up to
-// kStaticT frames (12.4 MiB), one copy per device, held until the process
+// kStaticT frames (4.6 MiB), one copy per device, held until the process
 // ends.  In host code `scratch` names a host-side stand-in, not the device
 // array: its device address comes from hipGetSymbolAddress, once per device.
 constexpr int kStaticT = 256;
@@ -602,9 +561,17 @@ int clutter_basis_size(int T, int k_lo, int k_hi) {
 hipError_t launch_clutter_filter(const float* x, int T, long long N, int k_lo, int k_hi, float* sv,
                                  float* pd, float* xf, void* ws, int cus, hipStream_t st) {
   char* w = static_cast<char*>(ws);
-  double* G = reinterpret_cast<double*>(w);
-  double* V = reinterpret_cast<double*>(w + align256(sizeof(double) * (size_t)T * T));
-  float* Bm = reinterpret_cast<float*>(w + 2 * align256(sizeof(double) * (size_t)T * T));
+  const ClutterWs L = ws_layout(T);
+  double* G = reinterpret_cast<double*>(w + L.G);
+  double* V = reinterpret_cast<double*>(w + L.V);
+  double* A = reinterpret_cast<double*>(w + L.A);
+  double* Y = reinterpret_cast<double*>(w + L.Y);
+  double* sc = reinterpret_cast<double*>(w + L.sc);
+  float* Bm = reinterpret_cast<float*>(w + L.Bm);
+  double* d = reinterpret_cast<double*>(w + L.d);
+  double* e_ = reinterpret_cast<double*>(w + L.e);
+  double* tau = reinterpret_cast<double*>(w + L.tau);
+  double* lam = reinterpret_cast<double*>(w + L.lam);
   const int kept = k_hi - k_lo;
   const int keep = kept <= T - kept ? 1 : 0;
   const int nb = keep ? kept : T - kept;
@@ -619,26 +586,17 @@ hipError_t launch_clutter_filter(const float* x, int T, long long N, int k_lo, i
   hipLaunchKernelGGL(gram_mfma, dim3((unsigned)npairs, (unsigned)nch), dim3(256), 0, st, x, T, N,
                      csz, nbk, G);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (T <= kFastT) {
-    char* w2 = w + 2 * align256(sizeof(double) * (size_t)T * T) + align256(sizeof(float) * (size_t)T * 64);
-    Rot* log = reinterpret_cast<Rot*>(w2);
-    float* lam = reinterpret_cast<float*>(w2 + rot_log_bytes(T));
-    int* nrot = reinterpret_cast<int*>(w2 + rot_log_bytes(T) + align256(sizeof(float) * (size_t)T));
-    const size_t lds = sizeof(float) * (size_t)T * (T + 1) / 2;
-    if (lds > 65536) {
-      e = hipFuncSetAttribute((const void*)jacobi_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(jacobi_lds, dim3(1), dim3(1024), lds, st, G, T, log, nrot, lam);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(replay_rotations, dim3(T), dim3(64), 0, st, log, nrot, T, V);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    double* W = reinterpret_cast<double*>(w2 + rot_log_bytes(T) + align256(sizeof(float) * (size_t)T) + 256);
-    hipLaunchKernelGGL(rank_refine_basis, dim3(1), dim3(1024), 0, st, lam, V, G, W, T, k_lo, k_hi, keep,
-                       sv, Bm, nb);
-  } else {
-    hipLaunchKernelGGL(jacobi_eig, dim3(1), dim3(1024), 0, st, G, V, T, k_lo, k_hi, keep, sv, Bm, nb);
-  }
+  hipLaunchKernelGGL(tri_reduce, dim3(1), dim3(1024), 0, st, G, T, A, d, e_, tau);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(tri_bisect, dim3(T), dim3(64), 0, st, d, e_, T, lam);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(tri_inverse, dim3((T + 63) / 64), dim3(64), 0, st, d, e_, lam, T, sc, Y);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(tri_orth, dim3(1), dim3(1024), 0, st, lam, T, Y);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(tri_back, dim3(T), dim3(256), 0, st, A, tau, Y, T, V);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(rank_basis, dim3(1), dim3(1024), 0, st, lam, V, T, k_lo, k_hi, keep, sv, Bm, nb);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (nb == 0) {  // keep nothing or remove nothing
     return launch_project<1>(x, T, N, Bm, 0, keep, pd, xf, st);

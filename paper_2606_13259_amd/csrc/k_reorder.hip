@@ -56,6 +56,62 @@ __global__ __launch_bounds__(256) void copy_convert(const float* __restrict__ y,
   }
 }
 
+// Contiguous output (one item: ws has the layout of y): each thread moves
+// four 16-byte loads of four samples each, all issued before the first
+// conversion, and writes each group of four converted samples with one
+// vector store (16, 8 or 4 bytes).
+template <class T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<_Float16> { using type = uint2; };
+template <> struct Vec4<uint16_t> { using type = uint2; };
+template <> struct Vec4<uint8_t> { using type = uint32_t; };
+
+template <class T>
+__device__ inline typename Vec4<T>::type cvt4(float4 v, int e) {
+  if constexpr (__is_same(T, float)) {
+    return v;
+  } else if constexpr (__is_same(T, uint8_t)) {
+    return e4m3_bits(ldexpf(v.x, e)) | (e4m3_bits(ldexpf(v.y, e)) << 8) |
+           (e4m3_bits(ldexpf(v.z, e)) << 16) | ((uint32_t)e4m3_bits(ldexpf(v.w, e)) << 24);
+  } else {
+    T h[4];
+    store_cvt(&h[0], v.x, e);
+    store_cvt(&h[1], v.y, e);
+    store_cvt(&h[2], v.z, e);
+    store_cvt(&h[3], v.w, e);
+    uint2 r;
+    __builtin_memcpy(&r, h, sizeof(r));
+    return r;
+  }
+}
+
+constexpr int kCopyUnroll = 4;
+template <class T>
+__global__ __launch_bounds__(256) void copy_convert_contig(const float* __restrict__ y, size_t n4,
+                                                           T* __restrict__ out,
+                                                           const float* __restrict__ amax, int item) {
+  using V = typename Vec4<T>::type;
+  const int e = item_exponent<T>(amax, item);
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4* src = reinterpret_cast<const f4*>(y);
+  V* dst = reinterpret_cast<V*>(out);
+  const size_t per_block = (size_t)blockDim.x * kCopyUnroll;
+  const size_t base = (size_t)blockIdx.x * per_block + threadIdx.x;
+  float4 v[kCopyUnroll];
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const size_t i = base + (size_t)u * blockDim.x;
+    f4 w = {0.f, 0.f, 0.f, 0.f};
+    if (i < n4) w = __builtin_nontemporal_load(src + i);
+    v[u] = float4{w.x, w.y, w.z, w.w};
+  }
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const size_t i = base + (size_t)u * blockDim.x;
+    if (i < n4) dst[i] = cvt4<T>(v[u], e);
+  }
+}
+
 // nb >= 2: transpose through LDS, 64 positions (q, m, k flattened) x up to 64
 // batch items per block.
 template <class T>
@@ -131,7 +187,14 @@ hipError_t reorder_t(const Geom& g, const float* y, int b0, int nb, int btot, vo
     hipError_t e = launch_item_absmax(g, y, b0, nb, const_cast<float*>(g.amax), st);
     if (e != hipSuccess) return e;
   }
-  if (nb == 1 && (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
+  const bool aligned = (reinterpret_cast<uintptr_t>(y) & 15) == 0 &&
+                       (reinterpret_cast<uintptr_t>(ws) & (4 * sizeof(T) - 1)) == 0;
+  if (nb == 1 && btot == 1 && aligned && nqmk % 4 == 0) {
+    const size_t n4 = (size_t)nqmk / 4;
+    const size_t blocks = (n4 + 256 * kCopyUnroll - 1) / (256 * kCopyUnroll);
+    hipLaunchKernelGGL(copy_convert_contig<T>, dim3((unsigned)blocks), dim3(256), 0, st, y, n4, out,
+                       g.amax, b0);
+  } else if (nb == 1 && (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
     const size_t blocks = (size_t)std::min<long long>((nqmk / 4 + 255) / 256 + 1, 65536);
     hipLaunchKernelGGL(copy_convert<T>, dim3((unsigned)blocks), dim3(256), 0, st, y,
                        (size_t)nqmk, out, (size_t)btot, (size_t)b0, g.amax);

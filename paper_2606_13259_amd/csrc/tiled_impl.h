@@ -146,9 +146,19 @@ __device__ inline void stage_load(Stage<BT, QN, MC>& st, const T* __restrict__ w
       const T* chan = ws + ((size_t)qt * M + m) * (size_t)K * B + b0;
       const int j = j0 + lane;
       if (lane < W && j >= 0 && j < K) {
+        const T* src = chan + (size_t)j * B;
+        // the BT items of a sample are contiguous (batch-inner): one vector
+        // load when they are all present and aligned
+        if (BT > 1 && b0 + BT <= B && (reinterpret_cast<uintptr_t>(src) & (BT * sizeof(T) - 1)) == 0) {
+          typedef T vecT __attribute__((ext_vector_type(BT)));
+          const vecT u = *reinterpret_cast<const vecT*>(src);
 #pragma unroll
-        for (int b = 0; b < BT; ++b)
-          if (b0 + b < B) st.v[k][b] = to_f32<T>(chan[j * B + b]);
+          for (int b = 0; b < BT; ++b) st.v[k][b] = to_f32<T>(u[b]);
+        } else {
+#pragma unroll
+          for (int b = 0; b < BT; ++b)
+            if (b0 + b < B) st.v[k][b] = to_f32<T>(src[b]);
+        }
       }
     }
   }

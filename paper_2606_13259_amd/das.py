@@ -29,6 +29,7 @@ APOD_UNIFORM, APOD_HANN = 0, 1
 ALGO = {"auto": 0, "plain": 1, "tiled": 2, "mfma": 3}
 ALGO_NAME = {v: k for k, v in ALGO.items()}
 DAS_INTERP_LINEAR, DAS_INTERP_CUBIC = 0, 1
+MFMA_FORM = {"auto": 0, "column": 1, "slab": 2, "persistent": 3}
 
 
 class DasError(RuntimeError):
@@ -102,6 +103,8 @@ def lib():
             "das_debug_delays": [_P, _I, _I, _I, _I, _I, _P, _P],
             "das_plan_set_iq": [_P, _I, ctypes.c_double],
             "das_plan_set_interp": [_P, _I],
+            "das_plan_set_mfma_form": [_P, _I],
+            "das_plan_get_mfma_form": [_P, ctypes.POINTER(_I)],
             "das_clutter_workspace_bytes": [_I, ctypes.POINTER(ctypes.c_size_t)],
             "das_clutter_filter": [_P, _I, ctypes.c_int64, _I, _I, _P, _P, _P, _P, _P],
             "das_clutter_filter_noalloc": [_P, _I, ctypes.c_int64, _I, _I, _P, _P, _P, _P],
@@ -328,6 +331,16 @@ class Plan:
         Lagrange through samples k-1 .. k+2; windowed algorithm, f32 storage)."""
         code = {"linear": DAS_INTERP_LINEAR, "cubic": DAS_INTERP_CUBIC}[interp]
         _check(lib().das_plan_set_interp(self.handle, code), "das_plan_set_interp")
+
+    def set_mfma_form(self, form: str):
+        """Launch form of the MFMA algorithm: "auto", "column" (4x4x4 voxel
+        columns per wavefront), "slab" (8x8x1 slabs) or "persistent"."""
+        _check(lib().das_plan_set_mfma_form(self.handle, MFMA_FORM[form]), "das_plan_set_mfma_form")
+
+    def mfma_form(self) -> str:
+        v = _I()
+        _check(lib().das_plan_get_mfma_form(self.handle, ctypes.byref(v)), "das_plan_get_mfma_form")
+        return {k: f for f, k in MFMA_FORM.items()}[v.value]
 
     def set_algo(self, algo: str):
         _check(lib().das_plan_set_algo(self.handle, ALGO[algo]), "das_plan_set_algo")

@@ -328,14 +328,16 @@ CFG4_SEED_BASE = 5
 
 
 def cfg4_ensemble(frames: int = 256, device="cuda", which=None, g: Optional[Geometry] = None,
-                  progress=None):
+                  progress=None, dtype=None):
     """Doppler-style ensemble at the cfg2 geometry: the cfg2 scatterers (200
     targets, seed 3; 1e4 speckle, seed 4) moved by the per-frame random walk
     N(0, (lambda/40)^2) per axis (seed 5 + frame), each frame simulated and
     normalised like cfg2_data (frame 0 is the cfg2 frame).  Returns
     (g, y[F, Q, M, K] float32 on `device`, frame numbers), F = frames, or
     only the frames listed in ``which``.  ``progress(done, total)`` is called
-    after every 32nd simulated frame."""
+    after every 32nd simulated frame; ``dtype`` is the simulator's working
+    precision (FP64 by default; FP32 simulates a 256-frame ensemble several
+    times faster, the arrival times then carrying ~1e-4 sample of rounding)."""
     import torch
     g = cfg2() if g is None else g
     s = scatterers(g, 200, 10_000, seed_targets=3, seed_speckle=4)
@@ -344,7 +346,7 @@ def cfg4_ensemble(frames: int = 256, device="cuda", which=None, g: Optional[Geom
     ids = list(range(frames)) if which is None else [int(f) for f in which]
     y = torch.empty(len(ids), g.Q, g.M, g.K, dtype=torch.float32, device=device)
     for i, f in enumerate(ids):
-        y[i] = simulate(g, Scatterers(pos[f], s.amp), device=device)
+        y[i] = simulate(g, Scatterers(pos[f], s.amp), device=device, dtype=dtype)
         if progress is not None and (i + 1) % 32 == 0:
             progress(i + 1, len(ids))
     return g, y, ids

@@ -64,15 +64,17 @@ def test_motion_frames_are_distinct(gpu):
     assert d0_255 > d01
 
 
-@pytest.mark.parametrize("storage", ["f16", "fp8"])
-def test_ensemble_256_frames_mfma(gpu, storage):
+@pytest.mark.parametrize("storage,form", [("f16", "auto"), ("f16", "slab"), ("fp8", "auto"),
+                                          ("fp8", "slab")])
+def test_ensemble_256_frames_mfma(gpu, storage, form):
     das = _das()
     c = _ensemble(gpu)
     plan = das.Plan(c["g"], max_batch=B, storage=storage)
+    plan.set_mfma_form(form)
     assert plan.algo(B) == "mfma"
-    say(f"cfg4 ensemble: {B} motion frames, {storage} MFMA")
+    say(f"cfg4 ensemble: {B} motion frames, {storage} MFMA, {form} form")
     x = plan.forward(c["y"])
-    _check_frames(x, c, storage, f"{storage} mfma")
+    _check_frames(x, c, storage, f"{storage} mfma {form}")
     plan.close()
 
 

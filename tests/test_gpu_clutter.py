@@ -136,6 +136,6 @@ def test_workspace_is_reused(gpu):
 
 
 def test_more_than_256_frames(gpu):
-    """T = 300: the FP64 Jacobi on global memory (no LDS copy), same bars."""
+    """T = 300 (above the allocation-free buffer's limit), same bars."""
     x, vessel = synth.doppler_ensemble((12, 10, 8), T=300, seed=300)
     _check(x, 3, 300, gpu, "T = 300, remove 3", filtered=True)
