@@ -151,16 +151,24 @@ das_status das_plan_set_iq(das_plan p, int32_t enable, double fc);
  * each wavefront an 8 x 8 x 1 slab (four groups side by side at one depth,
  * whose taps share more sample chunks).  DAS_MFMA_PERSISTENT: the persistent
  * dynamic-scheduling kernel of das_forward_batched with one plan (4 x 4 x 4
- * columns).  DAS_MFMA_AUTO (default): persistent where it gives the plan the
+ * columns).  DAS_MFMA_COLUMN_FP8 / DAS_MFMA_SLAB_FP8 (FP8 storage only,
+ * DAS_ERR_UNSUPPORTED otherwise): the COLUMN / SLAB launches on the FP8
+ * matrix instructions, contracting the stored E4M3 codes with E4M3
+ * interpolation weights (each weight, scaled by 2^7, split into two E4M3
+ * parts: a relative weight error near 2^-8 instead of the f16 weights'
+ * 2^-11).  DAS_MFMA_AUTO (default): persistent where it gives the plan the
  * same batch tiles per wavefront as the plain launch, else COLUMN.  All forms
- * read the same workspace and agree up to FP32 summation order and the f16
+ * read the same workspace and agree up to FP32 summation order and the
  * rounding of the interpolation weights (they form delays relative to
- * different box centres). */
+ * different box centres).  FP8 storage is Sec. 5's lower-precision future
+ * direction. */
 typedef enum {
   DAS_MFMA_AUTO = 0,
   DAS_MFMA_COLUMN = 1,
   DAS_MFMA_SLAB = 2,
-  DAS_MFMA_PERSISTENT = 3
+  DAS_MFMA_PERSISTENT = 3,
+  DAS_MFMA_COLUMN_FP8 = 4,
+  DAS_MFMA_SLAB_FP8 = 5
 } das_mfma_form;
 das_status das_plan_set_mfma_form(das_plan p, int32_t form);
 das_status das_plan_get_mfma_form(das_plan p, int32_t* form);
@@ -253,8 +261,8 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
 /* Tile shapes picked by measurement, as Sec. 3.2 says they should be chosen
  * ("determined by profiling").  For a plan whose algorithm for `batch` items
  * is the windowed one, times the candidate tile shapes; for the MFMA
- * algorithm, times the launch forms COLUMN, SLAB and PERSISTENT
- * (das_mfma_form).  Runs on `stream` with
+ * algorithm, times the launch forms COLUMN, SLAB and PERSISTENT (and for
+ * FP8 storage COLUMN_FP8 and SLAB_FP8; das_mfma_form).  Runs on `stream` with
  * scratch buffers it allocates and frees (a zeroed workspace of `batch`
  * items), keeps the fastest for this plan and synchronizes the stream. */
 das_status das_autotune(das_plan p, int32_t batch, void* stream);

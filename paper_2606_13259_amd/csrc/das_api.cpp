@@ -452,8 +452,11 @@ das_status das_plan_set_algo(das_plan p, int32_t algo) {
 
 das_status das_plan_set_mfma_form(das_plan p, int32_t form) {
   if (das_status s = check_plan(p)) return s;
-  if (form < DAS_MFMA_AUTO || form > DAS_MFMA_PERSISTENT)
+  if (form < DAS_MFMA_AUTO || form > DAS_MFMA_SLAB_FP8)
     return fail(DAS_ERR_INVALID_ARG, "unknown MFMA form");
+  if ((form == DAS_MFMA_COLUMN_FP8 || form == DAS_MFMA_SLAB_FP8) &&
+      p->cfg.storage != DAS_STORE_FP8_E4M3)
+    return fail(DAS_ERR_UNSUPPORTED, "FP8 matrix operands need FP8 storage");
   p->mfma_form = form;
   return DAS_OK;
 }
@@ -575,7 +578,9 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
     // the persistent kernel with one plan: same results, dynamic balance
     return forward_batched_mfma(1, &p, &ws, &batch, &x, stream);
   } else {
-    e = launch_mfma_forward(g, p->cfg.storage, ws, batch, x, p->mfma_form == DAS_MFMA_SLAB, st);
+    const int f = p->mfma_form;
+    e = launch_mfma_forward(g, p->cfg.storage, ws, batch, x, f == DAS_MFMA_SLAB || f == DAS_MFMA_SLAB_FP8,
+                            f == DAS_MFMA_COLUMN_FP8 || f == DAS_MFMA_SLAB_FP8, st);
   }
   if (e != hipSuccess) return hip_fail(e, "das_forward launch");
   return DAS_OK;
@@ -724,8 +729,10 @@ static das_status autotune_mfma(das_plan p, int32_t batch, hipStream_t st) {
   int best = -1;
   float best_ms = 1e30f;
   das_status ds = DAS_OK;
-  const int forms[3] = {DAS_MFMA_COLUMN, DAS_MFMA_SLAB, DAS_MFMA_PERSISTENT};
-  for (int fi = 0; fi < 3 && e == hipSuccess && ds == DAS_OK; ++fi) {
+  const int forms[5] = {DAS_MFMA_COLUMN, DAS_MFMA_SLAB, DAS_MFMA_PERSISTENT, DAS_MFMA_COLUMN_FP8,
+                        DAS_MFMA_SLAB_FP8};
+  const int nforms = p->cfg.storage == DAS_STORE_FP8_E4M3 ? 5 : 3;
+  for (int fi = 0; fi < nforms && e == hipSuccess && ds == DAS_OK; ++fi) {
     p->mfma_form = forms[fi];
     ds = das_forward(p, ws, batch, x, st);  // warm-up
     if (ds == DAS_OK) e = hipEventRecord(e0, st);

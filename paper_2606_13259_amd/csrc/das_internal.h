@@ -129,9 +129,11 @@ hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, i
 size_t mfma_workspace_elems(const Geom& g, int B);  // samples (1, 2 bytes each)
 hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b0, int nb, int btot,
                                void* ws, hipStream_t st);
-// Plain MFMA launch with 4 x 4 x 4 wavefront columns, or 8 x 8 x 1 slabs.
+// Plain MFMA launch with 4 x 4 x 4 wavefront columns, or 8 x 8 x 1 slabs;
+// FP8 storage: fp8_operands contracts the stored codes with FP8 weights on
+// the FP8 matrix instructions instead of decoding them to f16.
 hipError_t launch_mfma_forward(const Geom& g, int storage, const void* ws, int B, float* x,
-                               bool slab, hipStream_t st);
+                               bool slab, bool fp8_operands, hipStream_t st);
 
 // Windowed forward, one instantiation set per storage type.
 hipError_t tiled_forward_f32(const Geom& g, const TileShape& ts, const Window& w, const void* ws,

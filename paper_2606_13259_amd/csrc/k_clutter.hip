@@ -138,15 +138,19 @@ __device__ inline double block_sum(double v, double* red) {
 // FP64 keeps every eigenvector accurate to ~1e-16 of the largest eigenvalue
 // over its gap, also for the weak components of a wide dynamic range.
 
-// 1. A: working copy of G (full, row-major); on return the Householder vector
-// u_k (its entries k+1 .. T-1, the first scaled to u_k[k+1]) sits in column k
-// below the diagonal.
+// 1. A: working copy of G (full, row-major, mirrored from the upper triangle
+// that the Gram kernel forms); on return column k below the diagonal holds
+// the Householder vector u_k (entries k+1 .. T-1).
 __global__ __launch_bounds__(1024) void tri_reduce(const double* __restrict__ G, int T,
                                                    double* __restrict__ A, double* __restrict__ d,
                                                    double* __restrict__ e, double* __restrict__ tau) {
   __shared__ double v[kMaxT], w[kMaxT], red[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  for (int i = tid; i < T * T; i += blockDim.x) A[i] = G[i];
+  // G holds the upper triangle (the Gram kernel forms blocks I <= J)
+  for (int w = tid; w < T * T; w += blockDim.x) {
+    const int i = w / T, j = w - i * T;
+    A[w] = i <= j ? G[w] : G[(size_t)j * T + i];
+  }
   __syncthreads();
   for (int k = 0; k + 2 < T; ++k) {
     const int n = T - k - 1;  // the trailing block is rows / columns k+1 .. T-1

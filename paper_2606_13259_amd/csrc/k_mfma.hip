@@ -62,11 +62,11 @@ struct Box {
   static constexpr int GX = X, GY = Y, GZ = Z, ZS = X * Y * Z;
 };
 
-template <class S, class BX, int NB, int QN, bool WTX>
+template <class S, class BX, int NB, int QN, bool WTX, class OP = Operand<S>>
 __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ ws, int B, int TW,
                                            int Kc, float* __restrict__ x, int ngx, int ngy,
                                            int col, int by, float* __restrict__ bq_lds) {
-  using T = typename Operand<S>::T;
+  using T = typename OP::T;
   constexpr int GX = BX::GX, GY = BX::GY, GZ = BX::GZ, ZS = BX::ZS;
   // chunks loaded per step before the rare second pass
   constexpr int NCH = GZ == 1 ? 3 : GZ / 2 + 2;
@@ -223,9 +223,7 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
             const bool valid = live && w[k] != 0.f && t[k] >= -1 && t[k] <= K - 1;
             const float wt = valid ? (WTX ? w[k] * wqv[k] : w[k]) : 0.f;
             const float w2 = wt * al, w1 = wt - w2;
-            P[k] = Mma<T>::pack(w1, w2);
-            Plo[k] = 0;
-            if constexpr (Mma<T>::kSplit) Plo[k] = Mma<T>::pack(w1 - bf16_value(w1), w2 - bf16_value(w2));
+            Mma<T>::pack2(w1, w2, P[k], Plo[k]);
             lo = valid ? min(lo, t[k]) : lo;
             hi = valid ? max(hi, t[k]) : hi;
             t[k] = valid ? t[k] : -BIG;
@@ -242,20 +240,20 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
 #pragma unroll
           for (int k = 0; k < ZS; ++k) d[k] = t[k] > -BIG ? t[k] + CH - CH * c_lo : -BIG;
           for (int u0 = 0; u0 < nc; u0 += NCH) {
-            typename Operand<S>::Raw Br[NCH][NB];
-            u32x4 Bf[NCH][NB];
+            typename OP::Raw Br[NCH][NB];
+            typename OP::Frag Bf[NCH][NB];
 #pragma unroll
             for (int u = 0; u < NCH; ++u)
               if (u0 + u < nc) {
                 const S* pc = cqq + (size_t)min(c_lo + u0 + u, Kc - 1) * chunk_el;
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) Br[u][nb] = Operand<S>::load(pc + nb * 16 * CH);
+                for (int nb = 0; nb < NB; ++nb) Br[u][nb] = OP::load(pc + nb * 16 * CH);
               }
 #pragma unroll
             for (int u = 0; u < NCH; ++u)
               if (u0 + u < nc) {
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) Bf[u][nb] = Operand<S>::decode(Br[u][nb]);
+                for (int nb = 0; nb < NB; ++nb) Bf[u][nb] = OP::decode(Br[u][nb]);
               }
 #pragma unroll
             for (int k = 0; k < ZS; ++k) {
@@ -265,11 +263,11 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
                 const int du = d[k] - CH * (u0 + u);
                 // does any lane hold a tap of group k in this chunk?
                 if (__ballot((unsigned)(du + 1) <= (unsigned)CH) == 0ull) continue;
-                const u32x4 A = place_pair(P[k], du);
+                const typename Mma<T>::Frag A = Mma<T>::place(P[k], du);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) acc[k][nb] = Mma<T>::mma(A, Bf[u][nb], acc[k][nb]);
                 if constexpr (Mma<T>::kSplit) {
-                  const u32x4 Al = place_pair(Plo[k], du);
+                  const typename Mma<T>::Frag Al = Mma<T>::place(Plo[k], du);
 #pragma unroll
                   for (int nb = 0; nb < NB; ++nb) acc[k][nb] = Mma<T>::mma(Al, Bf[u][nb], acc[k][nb]);
                 }
@@ -299,7 +297,7 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
         const int jx = bx0 + 4 * kx + r;
         if (jx < g.n[0]) {
           if constexpr (__is_same(S, uint8_t))
-            xb[jx] = ldexpf(acc[k][nb][r], -e);
+            xb[jx] = ldexpf(acc[k][nb][r] * (1.f / Mma<T>::kScale), -e);
           else
             xb[jx] = acc[k][nb][r];
         }
@@ -320,14 +318,14 @@ __device__ inline int xcd_remap(int b, int nblocks) {
   return r * per + (k % X) * C + k / X;
 }
 
-template <class T, class BX, int NB, int QN, bool WTX>
+template <class T, class BX, int NB, int QN, bool WTX, class OP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 2 : 3))) void mfma_forward_stack(
     Geom g, const T* __restrict__ ws, int B, int TW, int Kc, float* __restrict__ x, int ngx,
     int ngy, int ncols) {
   __shared__ __align__(16) float bq_lds[4 * QN * 64 * BX::ZS * (WTX ? 2 : 1)];
   const int col = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (col >= ncols) return;  // whole wavefront
-  stack_body<T, BX, NB, QN, WTX>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y, bq_lds);
+  stack_body<T, BX, NB, QN, WTX, OP>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y, bq_lds);
 }
 
 // Voxel groups per wavefront box: a 4 x 4 x 4 column (four 4 x 4 groups
@@ -440,46 +438,46 @@ __global__ __launch_bounds__(256) void reorder_chunks(const float* __restrict__ 
   }
 }
 
-template <class T, class BX, int NB, int QN, bool WTX>
+template <class T, class BX, int NB, int QN, bool WTX, class OP>
 hipError_t launch_stack_t(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
   const int ngx = (g.n[0] + 4 * BX::GX - 1) / (4 * BX::GX), ngy = (g.n[1] + 4 * BX::GY - 1) / (4 * BX::GY);
   const int ncols = ngx * ngy * ((g.n[2] + BX::GZ - 1) / BX::GZ);
   const int TW = mfma_tile_width(B), Kc = mfma_chunks(g.K);
   dim3 grid((ncols + 3) / 4, mfma_batch_pad(B) / (16 * NB));
-  hipLaunchKernelGGL((mfma_forward_stack<T, BX, NB, QN, WTX>), grid, dim3(256), 0, st, g,
+  hipLaunchKernelGGL((mfma_forward_stack<T, BX, NB, QN, WTX, OP>), grid, dim3(256), 0, st, g,
                      static_cast<const T*>(ws), B, TW, Kc, x, ngx, ngy, ncols);
   return hipGetLastError();
 }
 
-template <class T, class BX, int NB>
+template <class T, class BX, int NB, class OP>
 hipError_t launch_stack(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
   constexpr int QMAX = BX::ZS >= 8 ? 4 : 8;
   const bool wtx = g.w_tx != nullptr;
   const int qg = g.Q == 1 ? 1 : (g.Q <= 4 || QMAX == 4) ? 4 : 8;
   if (qg == 1)
-    return wtx ? launch_stack_t<T, BX, NB, 1, true>(g, ws, B, x, st)
-               : launch_stack_t<T, BX, NB, 1, false>(g, ws, B, x, st);
+    return wtx ? launch_stack_t<T, BX, NB, 1, true, OP>(g, ws, B, x, st)
+               : launch_stack_t<T, BX, NB, 1, false, OP>(g, ws, B, x, st);
   if (qg == 4)
-    return wtx ? launch_stack_t<T, BX, NB, 4, true>(g, ws, B, x, st)
-               : launch_stack_t<T, BX, NB, 4, false>(g, ws, B, x, st);
-  return wtx ? launch_stack_t<T, BX, NB, QMAX, true>(g, ws, B, x, st)
-             : launch_stack_t<T, BX, NB, QMAX, false>(g, ws, B, x, st);
+    return wtx ? launch_stack_t<T, BX, NB, 4, true, OP>(g, ws, B, x, st)
+               : launch_stack_t<T, BX, NB, 4, false, OP>(g, ws, B, x, st);
+  return wtx ? launch_stack_t<T, BX, NB, QMAX, true, OP>(g, ws, B, x, st)
+             : launch_stack_t<T, BX, NB, QMAX, false, OP>(g, ws, B, x, st);
 }
 
-template <class T, class BX>
+template <class T, class BX, class OP = Operand<T>>
 hipError_t launch_any(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
-  if (mfma_stack_tiles(B) == 4) return launch_stack<T, BX, 4>(g, ws, B, x, st);
-  if (mfma_stack_tiles(B) == 2) return launch_stack<T, BX, 2>(g, ws, B, x, st);
-  return launch_stack<T, BX, 1>(g, ws, B, x, st);
+  if (mfma_stack_tiles(B) == 4) return launch_stack<T, BX, 4, OP>(g, ws, B, x, st);
+  if (mfma_stack_tiles(B) == 2) return launch_stack<T, BX, 2, OP>(g, ws, B, x, st);
+  return launch_stack<T, BX, 1, OP>(g, ws, B, x, st);
 }
 
 // Wavefront boxes of the plain (non-persistent) launch: a 4 x 4 x 4 column or
 // an 8 x 8 x 1 slab (four lateral groups at one depth, whose taps cluster
 // more tightly: fewer chunk loads per voxel).
 using kSlab = Box<2, 2, 1>;
-template <class T>
+template <class T, class OP = Operand<T>>
 hipError_t launch_box(const Geom& g, const void* ws, int B, float* x, bool slab, hipStream_t st) {
-  return slab ? launch_any<T, kSlab>(g, ws, B, x, st) : launch_any<T, kBox>(g, ws, B, x, st);
+  return slab ? launch_any<T, kSlab, OP>(g, ws, B, x, st) : launch_any<T, kBox, OP>(g, ws, B, x, st);
 }
 
 template <class T, int QN, bool WTX, int NBMAX>
@@ -598,9 +596,11 @@ hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b
 }
 
 hipError_t launch_mfma_forward(const Geom& g, int storage, const void* ws, int B, float* x,
-                               bool slab, hipStream_t st) {
+                               bool slab, bool fp8_operands, hipStream_t st) {
   if (storage == DAS_STORE_F16) return launch_box<_Float16>(g, ws, B, x, slab, st);
-  if (storage == DAS_STORE_FP8_E4M3) return launch_box<uint8_t>(g, ws, B, x, slab, st);
+  if (storage == DAS_STORE_FP8_E4M3)
+    return fp8_operands ? launch_box<uint8_t, OperandFp8Raw>(g, ws, B, x, slab, st)
+                        : launch_box<uint8_t>(g, ws, B, x, slab, st);
   return launch_box<uint16_t>(g, ws, B, x, slab, st);
 }
 

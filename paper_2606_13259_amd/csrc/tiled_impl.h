@@ -614,8 +614,11 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
   }
 }
 
+// Four wavefronts per SIMD (128 VGPRs) for one and two items per thread; with
+// four items per thread (four accumulators, four-item tap registers and
+// staging) three (168 VGPRs), which leaves no spills.
 template <class T, int BT, int QN, bool WTX>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void tiled_forward(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BT >= 4 ? 3 : 4))) void tiled_forward(
     Geom g, TileShape ts, Window win, const T* __restrict__ ws, int B, float* __restrict__ x,
     int ntx, int nty, int ntiles) {
   extern __shared__ __align__(16) unsigned char smem[];

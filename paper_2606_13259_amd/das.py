@@ -29,7 +29,7 @@ APOD_UNIFORM, APOD_HANN = 0, 1
 ALGO = {"auto": 0, "plain": 1, "tiled": 2, "mfma": 3}
 ALGO_NAME = {v: k for k, v in ALGO.items()}
 DAS_INTERP_LINEAR, DAS_INTERP_CUBIC = 0, 1
-MFMA_FORM = {"auto": 0, "column": 1, "slab": 2, "persistent": 3}
+MFMA_FORM = {"auto": 0, "column": 1, "slab": 2, "persistent": 3, "column_fp8": 4, "slab_fp8": 5}
 
 
 class DasError(RuntimeError):
@@ -334,7 +334,8 @@ class Plan:
 
     def set_mfma_form(self, form: str):
         """Launch form of the MFMA algorithm: "auto", "column" (4x4x4 voxel
-        columns per wavefront), "slab" (8x8x1 slabs) or "persistent"."""
+        columns per wavefront), "slab" (8x8x1 slabs), "persistent", or for FP8
+        storage "column_fp8" / "slab_fp8" (FP8 matrix operands)."""
         _check(lib().das_plan_set_mfma_form(self.handle, MFMA_FORM[form]), "das_plan_set_mfma_form")
 
     def mfma_form(self) -> str:

@@ -18,6 +18,11 @@ pytestmark = pytest.mark.gpu
 
 KERNEL_REL = {"f16": 5e-4, "bf16": 5e-5, "fp8": 5e-4}
 KERNEL_ABS = {"f16": 1e-3, "bf16": 1e-4, "fp8": 1e-3}
+# FP8 matrix operands: each interpolation weight (scaled by 2^7) is carried
+# as two E4M3 parts, a relative error of at most 2^-8 (2^-9 on average with
+# round to nearest) instead of the f16 weights' 2^-11; on incoherent (random)
+# data the output error is of that relative size: bars 4e-3 / 8e-3.
+KERNEL_FP8W = (4e-3, 8e-3)
 FORMS = ["column", "slab", "persistent"]
 
 
@@ -26,12 +31,13 @@ def _das():
     return das
 
 
-def _check_both(x, y_np, g, storage, what, w_tx=None):
+def _check_both(x, y_np, g, storage, what, w_tx=None, kernel=None):
     xo = oracle.forward(y_np, g, w_tx=w_tx)
     xr = oracle.forward(round_like_storage(y_np, storage), g, w_tx=w_tx)
+    kb = kernel or (KERNEL_REL[storage], KERNEL_ABS[storage])
     for b in range(x.shape[0]):
         check_close(x[b], xo[b], *lowp_bars(storage), f"{what} b={b}")
-        check_close(x[b], xr[b], KERNEL_REL[storage], KERNEL_ABS[storage], f"  rounded data b={b}")
+        check_close(x[b], xr[b], *kb, f"  rounded data b={b}")
 
 
 def _ragged_geometry():
@@ -121,3 +127,40 @@ def test_autotune_picks_an_mfma_form(gpu):
     with pytest.raises(das.DasError) as e:
         das._check(das.lib().das_plan_set_mfma_form(p.handle, 7), "das_plan_set_mfma_form")
     assert e.value.status == das.DAS_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("form", ["column_fp8", "slab_fp8"])
+@pytest.mark.parametrize("B", [16, 40])
+def test_fp8_operand_forms(gpu, form, B):
+    """FP8 storage contracted on the FP8 matrix instructions (E4M3 weights)."""
+    g = _ragged_geometry()
+    y = synth.random_channel_data(g, B, seed=140 + B)
+    say(f"mfma {form} ragged {g.grid_dims}, B={B}")
+    x = _plan(g, B, "fp8", form).forward(y.to(gpu)).cpu().numpy()
+    idx = [0, B // 2, B - 1]
+    _check_both(x[idx], y.numpy()[idx], g, "fp8", f"{form} B={B}", kernel=KERNEL_FP8W)
+
+
+def test_fp8_operand_cfg2_full_volume_sampled(gpu):
+    g, y = cfg2_channel_data()
+    B = 64
+    yb = torch.cat([y[None], synth.random_channel_data(g, B - 1, seed=43, device=y.device)]).contiguous()
+    say(f"mfma slab_fp8 cfg2 full volume, B={B}")
+    x = _plan(g, B, "fp8", "slab_fp8").forward(yb)
+    items = [0, 63]
+    x = x[items].cpu().numpy()
+    idx = sample_voxels(g, 256, seed=20)
+    ynp = yb[items].cpu().numpy()
+    xo = oracle.forward(ynp, g, voxels=idx)
+    xr = oracle.forward(round_like_storage(ynp, "fp8"), g, voxels=idx)
+    for i, b in enumerate(items):
+        check_close(x[i][idx], xo[i], *lowp_bars("fp8"), f"item {b}, sampled voxels")
+        check_close(x[i][idx], xr[i], *KERNEL_FP8W, "  rounded data")
+
+
+def test_fp8_operand_forms_need_fp8_storage(gpu):
+    das = _das()
+    p = das.Plan(_ragged_geometry(), max_batch=16, storage="f16", algo="mfma")
+    with pytest.raises(das.DasError) as e:
+        p.set_mfma_form("slab_fp8")
+    assert e.value.status == das.DAS_ERR_UNSUPPORTED
