@@ -140,9 +140,12 @@ das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
  * exp(-i 2 pi fc t_k), t_k = t0 + k/fs.  das_forward then writes
  *   x[2b] + i x[2b+1] = sum_q sum_m w ((1-a) s(k) + a s(k+1)) exp(i 2 pi fc tau),
  * tau = (D_tx + D_rx)/c, from the interpolated complex samples s.  Runs in the
- * windowed algorithm with f32 storage and an even batch (DAS_ERR_UNSUPPORTED /
- * DAS_ERR_INVALID_ARG otherwise); das_adjoint, das_grad_sound_speed and
- * das_forward_batched refuse IQ plans.  enable = 0 restores real data. */
+ * windowed algorithm with f32 storage, or in the MFMA algorithm with f16 or
+ * FP8 storage (Alg. 3's complex W: the cosine and sine parts of the weights
+ * contracted with the same sample fragments; COLUMN or SLAB launch), with an
+ * even batch (DAS_ERR_UNSUPPORTED / DAS_ERR_INVALID_ARG otherwise);
+ * das_adjoint, das_grad_sound_speed and das_forward_batched refuse IQ plans.
+ * enable = 0 restores real data. */
 das_status das_plan_set_iq(das_plan p, int32_t enable, double fc);
 /* Launch form of the MFMA algorithm (Sec. 3.4, Alg. 3); Sec. 3.2 says tile
  * sizes should be picked by profiling, and das_autotune does so for MFMA

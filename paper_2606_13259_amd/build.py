@@ -39,7 +39,12 @@ def hipcc() -> str:
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    for attempt in range(3):
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        # an internal compiler crash (not a diagnostic in the source) has been
+        # seen to pass on a second run of the same command
+        if r.returncode == 0 or "PLEASE submit a bug report" not in r.stderr:
+            break
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj

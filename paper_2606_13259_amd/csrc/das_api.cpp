@@ -564,8 +564,21 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
     return fail(DAS_ERR_UNSUPPORTED, "cubic interpolation runs in the windowed algorithm on real data");
   if (p->iq) {
     if (batch % 2) return fail(DAS_ERR_INVALID_ARG, "complex baseband needs (I, Q) pairs: an even batch");
-    if (algo != DAS_ALGO_TILED || p->cfg.storage != DAS_STORE_F32)
-      return fail(DAS_ERR_UNSUPPORTED, "complex baseband runs in the windowed algorithm with f32 storage");
+    const bool tiled_ok = algo == DAS_ALGO_TILED && p->cfg.storage == DAS_STORE_F32;
+    const bool mfma_ok = algo == DAS_ALGO_MFMA && (p->cfg.storage == DAS_STORE_F16 ||
+                                                   p->cfg.storage == DAS_STORE_FP8_E4M3);
+    if (!tiled_ok && !mfma_ok)
+      return fail(DAS_ERR_UNSUPPORTED,
+                  "complex baseband runs in the windowed algorithm with f32 storage or the MFMA "
+                  "algorithm with f16 or fp8 storage");
+    if (mfma_ok) {
+      // column or slab launch (the persistent and FP8-operand forms are not built for IQ)
+      const int f = p->mfma_form;
+      e = launch_mfma_forward_iq(g, p->cfg.storage, ws, batch, x, f == DAS_MFMA_SLAB || f == DAS_MFMA_SLAB_FP8,
+                                 st);
+      if (e != hipSuccess) return hip_fail(e, "das_forward launch");
+      return DAS_OK;
+    }
   }
   if (algo == DAS_ALGO_PLAIN) {
     e = launch_plain_forward(g, static_cast<const float*>(ws), batch, x, st);

@@ -134,6 +134,9 @@ hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b
 // the FP8 matrix instructions instead of decoding them to f16.
 hipError_t launch_mfma_forward(const Geom& g, int storage, const void* ws, int B, float* x,
                                bool slab, bool fp8_operands, hipStream_t st);
+// Complex baseband (IQ) items in (I, Q) column pairs, f16 or FP8 storage.
+hipError_t launch_mfma_forward_iq(const Geom& g, int storage, const void* ws, int B, float* x,
+                                  bool slab, hipStream_t st);
 
 // Windowed forward, one instantiation set per storage type.
 hipError_t tiled_forward_f32(const Geom& g, const TileShape& ts, const Window& w, const void* ws,

@@ -26,18 +26,20 @@
 // (batch item b, receiver row r) is one 16-byte load (8 bytes for FP8), the
 // 16 lanes of a row read 256 (128) contiguous bytes, and the wavefronts of one
 // batch tile sweep one contiguous region.  FP8 (E4M3) codes are decoded to f16
-// operands in registers, exactly; the item's power-of-two scale is removed at
-// the output.
+// operands in registers, exactly, or (FP8-operand forms) contracted as they
+// are by the FP8 matrix instructions; the item's power-of-two scale is
+// removed at the output.
 //
-// A wavefront owns a column of kStack such groups stacked in depth: it loads
-// the union of their chunks once per receiver row and applies each loaded
-// chunk to every group of the column with taps in it, which divides the
-// L1/L2 traffic (the bound of this form) by up to the stack depth.
+// A wavefront owns a box of four such groups, a 4 x 4 x 4 column (groups
+// stacked in depth) or an 8 x 8 x 1 slab (groups side by side): it loads the
+// union of their chunks once per receiver row and applies each loaded chunk
+// to every group of the box with taps in it, which divides the L1/L2
+// traffic by up to four.
 //
 // Delay formation is the tile-relative FP32 scheme of the VALU kernels with
-// the column centre as reference.  Weights are rounded to the operand type;
-// for bf16 each weight is split into a high and a low bf16 part (two MFMAs
-// with the same samples) so that the weight rounding stays far below the
+// the box centre as reference.  Weights are rounded to the operand type; for
+// bf16 and FP8 operands each weight is split into a high and a low part (two
+// MFMAs with the same samples) so that the weight rounding stays below the
 // storage rounding.  Accumulation is FP32.
 #include "mfma_common.h"
 
@@ -62,7 +64,13 @@ struct Box {
   static constexpr int GX = X, GY = Y, GZ = Z, ZS = X * Y * Z;
 };
 
-template <class S, class BX, int NB, int QN, bool WTX, class OP = Operand<S>>
+// IQ: complex baseband items come in (I, Q) column pairs; every term is
+// remodulated by exp(i 2 pi fc tau).  Two accumulators take the same sample
+// fragments with the weights times cos and times sin of the phase; since the
+// sum is linear, I = acc_cos(I) - acc_sin(Q) and Q = acc_sin(I) + acc_cos(Q)
+// are combined once at the end (one lane exchange: columns 2c and 2c+1 are
+// neighbouring lanes).
+template <class S, class BX, int NB, int QN, bool WTX, class OP = Operand<S>, bool IQ = false>
 __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ ws, int B, int TW,
                                            int Kc, float* __restrict__ x, int ngx, int ngy,
                                            int col, int by, float* __restrict__ bq_lds) {
@@ -110,10 +118,15 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
   constexpr int BIG = 1 << 29;
 
   f32x4 acc[ZS][NB];
+  f32x4 acs[IQ ? ZS : 1][IQ ? NB : 1];  // IQ: sine-weighted accumulators
 #pragma unroll
   for (int k = 0; k < ZS; ++k)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[k][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int nb = 0; nb < NB; ++nb) {
+      acc[k][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (IQ) acs[k][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  const float fcfs_f = (float)g.fcfs;
 
   for (int q0 = 0; q0 < g.Q; q0 += QN) {
     const int qn = min(QN, g.Q - q0);
@@ -123,6 +136,13 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
     constexpr int PER = WTX ? 2 * ZS : ZS;
     float* bql = bq_lds + (size_t)(threadIdx.x >> 6) * QN * 64 * PER + lane * PER;
     const int my_ktx = mine.ktx;
+    // IQ: the transmit's phase term frac(fc/fs ktx + fc t0) in revolutions
+    // (FP64 before rounding: ktx reaches thousands)
+    float my_rq = 0.f;
+    if constexpr (IQ) {
+      const double rv = g.fcfs * (double)my_ktx + g.fct0;
+      my_rq = (float)(rv - floor(rv));
+    }
     // transmits of the group with a nonzero weight somewhere in this column
     // (sparse transmit lists, Sec. 5: the others contribute exact zeros)
     uint32_t qact = (1u << qn) - 1u;
@@ -191,6 +211,11 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
         const float en = __shfl(ren, src), h = __shfl(rh, src);
         const int krx = __shfl(rk, src);
         const int m = m0 + src;
+        float rm = 0.f;  // IQ: the receiver's phase term frac(fc/fs krx)
+        if constexpr (IQ) {
+          const double rv = g.fcfs * (double)krx;
+          rm = (float)(rv - floor(rv));
+        }
         float w[ZS], a[ZS];
         bool anyw = false;
 #pragma unroll
@@ -207,6 +232,7 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
           const bool live = q < qn;
           int t[ZS];
           uint32_t P[ZS], Plo[ZS];
+          uint32_t Ps[IQ ? ZS : 1];
           int lo = BIG, hi = -BIG;
           float bqv[ZS], wqv[ZS];
 #pragma unroll
@@ -215,6 +241,7 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
             wqv[k] = WTX ? bql[q * 64 * PER + ZS + k] : 1.f;
           }
           const int ktxq = __builtin_amdgcn_readlane(my_ktx, q);
+          const float rqq = IQ ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_rq), q)) : 0.f;
 #pragma unroll
           for (int k = 0; k < ZS; ++k) {
             const float f = a[k] + bqv[k];
@@ -222,8 +249,18 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
             const float al = frac_f32(f);
             const bool valid = live && w[k] != 0.f && t[k] >= -1 && t[k] <= K - 1;
             const float wt = valid ? (WTX ? w[k] * wqv[k] : w[k]) : 0.f;
-            const float w2 = wt * al, w1 = wt - w2;
-            Mma<T>::pack2(w1, w2, P[k], Plo[k]);
+            if constexpr (IQ) {
+              // revolutions fc/fs (ktx + krx + f) + fc t0, reduced to [0, 1)
+              // before the hardware sine and cosine (which take revolutions)
+              const float rev = frac_f32(rqq + rm + fcfs_f * f);
+              const float wc = wt * __builtin_amdgcn_cosf(rev), wsn = wt * __builtin_amdgcn_sinf(rev);
+              uint32_t unused;
+              Mma<T>::pack2(wc - wc * al, wc * al, P[k], Plo[k]);
+              Mma<T>::pack2(wsn - wsn * al, wsn * al, Ps[IQ ? k : 0], unused);
+            } else {
+              const float w2 = wt * al, w1 = wt - w2;
+              Mma<T>::pack2(w1, w2, P[k], Plo[k]);
+            }
             lo = valid ? min(lo, t[k]) : lo;
             hi = valid ? max(hi, t[k]) : hi;
             t[k] = valid ? t[k] : -BIG;
@@ -266,6 +303,12 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
                 const typename Mma<T>::Frag A = Mma<T>::place(P[k], du);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) acc[k][nb] = Mma<T>::mma(A, Bf[u][nb], acc[k][nb]);
+                if constexpr (IQ) {
+                  const typename Mma<T>::Frag As = Mma<T>::place(Ps[IQ ? k : 0], du);
+#pragma unroll
+                  for (int nb = 0; nb < NB; ++nb)
+                    acs[IQ ? k : 0][IQ ? nb : 0] = Mma<T>::mma(As, Bf[u][nb], acs[IQ ? k : 0][IQ ? nb : 0]);
+                }
                 if constexpr (Mma<T>::kSplit) {
                   const typename Mma<T>::Frag Al = Mma<T>::place(Plo[k], du);
 #pragma unroll
@@ -283,9 +326,26 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int b = tile * TW + col0 + nb * 16 + vi;
-    if (b >= B) continue;
     int e = 0;  // FP8: the item was stored as y 2^e
-    if constexpr (__is_same(S, uint8_t)) e = fp8_item_exponent(g.amax[b]);
+    if constexpr (__is_same(S, uint8_t)) e = fp8_item_exponent(g.amax[min(b, B - 1)]);
+    if constexpr (IQ) {
+      // each lane removes its own item's scale, then I = cos(I) - sin(Q) on
+      // even columns and Q = sin(I) + cos(Q) on odd ones
+#pragma unroll
+      for (int k = 0; k < ZS; ++k)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float c = acc[k][nb][r], sn = acs[IQ ? k : 0][IQ ? nb : 0][r];
+          if constexpr (__is_same(S, uint8_t)) {
+            c = ldexpf(c * (1.f / Mma<T>::kScale), -e);
+            sn = ldexpf(sn * (1.f / Mma<T>::kScale), -e);
+          }
+          const float ps = __shfl_xor(sn, 1);
+          acc[k][nb][r] = (vi & 1) ? ps + c : c - ps;
+        }
+      e = 0;
+    }
+    if (b >= B) continue;
 #pragma unroll
     for (int k = 0; k < ZS; ++k) {
       const int kx = k % GX, ky = (k / GX) % GY, kz = k / (GX * GY);
@@ -296,7 +356,7 @@ __device__ __forceinline__ void stack_body(const Geom& g, const S* __restrict__ 
       for (int r = 0; r < 4; ++r) {
         const int jx = bx0 + 4 * kx + r;
         if (jx < g.n[0]) {
-          if constexpr (__is_same(S, uint8_t))
+          if constexpr (__is_same(S, uint8_t) && !IQ)
             xb[jx] = ldexpf(acc[k][nb][r] * (1.f / Mma<T>::kScale), -e);
           else
             xb[jx] = acc[k][nb][r];
@@ -318,14 +378,14 @@ __device__ inline int xcd_remap(int b, int nblocks) {
   return r * per + (k % X) * C + k / X;
 }
 
-template <class T, class BX, int NB, int QN, bool WTX, class OP>
+template <class T, class BX, int NB, int QN, bool WTX, class OP, bool IQ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 2 : 3))) void mfma_forward_stack(
     Geom g, const T* __restrict__ ws, int B, int TW, int Kc, float* __restrict__ x, int ngx,
     int ngy, int ncols) {
   __shared__ __align__(16) float bq_lds[4 * QN * 64 * BX::ZS * (WTX ? 2 : 1)];
   const int col = xcd_remap(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (col >= ncols) return;  // whole wavefront
-  stack_body<T, BX, NB, QN, WTX, OP>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y, bq_lds);
+  stack_body<T, BX, NB, QN, WTX, OP, IQ>(g, ws, B, TW, Kc, x, ngx, ngy, col, blockIdx.y, bq_lds);
 }
 
 // Voxel groups per wavefront box: a 4 x 4 x 4 column (four 4 x 4 groups
@@ -438,30 +498,30 @@ __global__ __launch_bounds__(256) void reorder_chunks(const float* __restrict__ 
   }
 }
 
-template <class T, class BX, int NB, int QN, bool WTX, class OP>
+template <class T, class BX, int NB, int QN, bool WTX, class OP, bool IQ>
 hipError_t launch_stack_t(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
   const int ngx = (g.n[0] + 4 * BX::GX - 1) / (4 * BX::GX), ngy = (g.n[1] + 4 * BX::GY - 1) / (4 * BX::GY);
   const int ncols = ngx * ngy * ((g.n[2] + BX::GZ - 1) / BX::GZ);
   const int TW = mfma_tile_width(B), Kc = mfma_chunks(g.K);
   dim3 grid((ncols + 3) / 4, mfma_batch_pad(B) / (16 * NB));
-  hipLaunchKernelGGL((mfma_forward_stack<T, BX, NB, QN, WTX, OP>), grid, dim3(256), 0, st, g,
+  hipLaunchKernelGGL((mfma_forward_stack<T, BX, NB, QN, WTX, OP, IQ>), grid, dim3(256), 0, st, g,
                      static_cast<const T*>(ws), B, TW, Kc, x, ngx, ngy, ncols);
   return hipGetLastError();
 }
 
-template <class T, class BX, int NB, class OP>
+template <class T, class BX, int NB, class OP, bool IQ = false>
 hipError_t launch_stack(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
   constexpr int QMAX = BX::ZS >= 8 ? 4 : 8;
   const bool wtx = g.w_tx != nullptr;
   const int qg = g.Q == 1 ? 1 : (g.Q <= 4 || QMAX == 4) ? 4 : 8;
   if (qg == 1)
-    return wtx ? launch_stack_t<T, BX, NB, 1, true, OP>(g, ws, B, x, st)
-               : launch_stack_t<T, BX, NB, 1, false, OP>(g, ws, B, x, st);
+    return wtx ? launch_stack_t<T, BX, NB, 1, true, OP, IQ>(g, ws, B, x, st)
+               : launch_stack_t<T, BX, NB, 1, false, OP, IQ>(g, ws, B, x, st);
   if (qg == 4)
-    return wtx ? launch_stack_t<T, BX, NB, 4, true, OP>(g, ws, B, x, st)
-               : launch_stack_t<T, BX, NB, 4, false, OP>(g, ws, B, x, st);
-  return wtx ? launch_stack_t<T, BX, NB, QMAX, true, OP>(g, ws, B, x, st)
-             : launch_stack_t<T, BX, NB, QMAX, false, OP>(g, ws, B, x, st);
+    return wtx ? launch_stack_t<T, BX, NB, 4, true, OP, IQ>(g, ws, B, x, st)
+               : launch_stack_t<T, BX, NB, 4, false, OP, IQ>(g, ws, B, x, st);
+  return wtx ? launch_stack_t<T, BX, NB, QMAX, true, OP, IQ>(g, ws, B, x, st)
+             : launch_stack_t<T, BX, NB, QMAX, false, OP, IQ>(g, ws, B, x, st);
 }
 
 template <class T, class BX, class OP = Operand<T>>
@@ -469,6 +529,14 @@ hipError_t launch_any(const Geom& g, const void* ws, int B, float* x, hipStream_
   if (mfma_stack_tiles(B) == 4) return launch_stack<T, BX, 4, OP>(g, ws, B, x, st);
   if (mfma_stack_tiles(B) == 2) return launch_stack<T, BX, 2, OP>(g, ws, B, x, st);
   return launch_stack<T, BX, 1, OP>(g, ws, B, x, st);
+}
+
+// Complex baseband: twice the accumulators, so at most two batch tiles per
+// wavefront (a workspace tile of four is covered in two halves).
+template <class T, class BX>
+hipError_t launch_any_iq(const Geom& g, const void* ws, int B, float* x, hipStream_t st) {
+  if (mfma_stack_tiles(B) >= 2) return launch_stack<T, BX, 2, Operand<T>, true>(g, ws, B, x, st);
+  return launch_stack<T, BX, 1, Operand<T>, true>(g, ws, B, x, st);
 }
 
 // Wavefront boxes of the plain (non-persistent) launch: a 4 x 4 x 4 column or
@@ -593,6 +661,15 @@ hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b
                        b0, TW, static_cast<uint16_t*>(ws), nullptr);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_mfma_forward_iq(const Geom& g, int storage, const void* ws, int B, float* x,
+                                  bool slab, hipStream_t st) {
+  if (storage == DAS_STORE_F16)
+    return slab ? launch_any_iq<_Float16, kSlab>(g, ws, B, x, st) : launch_any_iq<_Float16, kBox>(g, ws, B, x, st);
+  if (storage == DAS_STORE_FP8_E4M3)
+    return slab ? launch_any_iq<uint8_t, kSlab>(g, ws, B, x, st) : launch_any_iq<uint8_t, kBox>(g, ws, B, x, st);
+  return hipErrorInvalidValue;  // bf16: not built (split weights)
 }
 
 hipError_t launch_mfma_forward(const Geom& g, int storage, const void* ws, int B, float* x,

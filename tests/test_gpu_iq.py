@@ -105,3 +105,61 @@ def test_iq_refusals(gpu):
     with pytest.raises(das.DasError) as e:
         p.set_iq(-1.0)
     assert e.value.status == das.DAS_ERR_INVALID_ARG
+
+
+# --- complex baseband in the MFMA locality form (Alg. 3 with complex W) ---
+# Bars: f16 / FP8 storage of the I and Q records against the oracle on the raw
+# complex data (the storage bars of the real forms), and the kernel alone
+# against the oracle on the values the workspace holds: the cosine- and
+# sine-weighted interpolation weights are f16 (relative rounding 2^-11), as in
+# the real MFMA form (5e-4 rel-L2, 1e-3 elementwise).
+MFMA_KERNEL = (5e-4, 1e-3)
+
+
+def _run_mfma(g, y_iq, fc, gpu, storage, form):
+    das = _das()
+    C = y_iq.shape[0]
+    lanes = np.empty((2 * C,) + y_iq.shape[1:], np.float32)
+    lanes[0::2] = y_iq.real
+    lanes[1::2] = y_iq.imag
+    plan = das.Plan(g, max_batch=2 * C, storage=storage, algo="mfma")
+    plan.set_iq(fc)
+    plan.set_mfma_form(form)
+    x = plan.forward(torch.from_numpy(lanes).to(gpu)).cpu().numpy().astype(np.float64)
+    return x[0::2] + 1j * x[1::2], lanes
+
+
+def _check_c(x, xo, rel, absf, what):
+    for c in range(x.shape[0]):
+        check_close(np.concatenate([x[c].real, x[c].imag]), np.concatenate([xo[c].real, xo[c].imag]),
+                    rel, absf, f"{what} item {c}")
+
+
+@pytest.mark.parametrize("form", ["column", "slab"])
+@pytest.mark.parametrize("storage", ["f16", "fp8"])
+@pytest.mark.parametrize("C", [8, 17, 32])
+def test_iq_mfma_random_records(gpu, form, storage, C):
+    """Random complex records, three transmit kinds, t0 != 0, ragged grid;
+    16, 34 and 64 batch columns (one tile, a ragged pair of 64-column tiles
+    covered in halves, two full tiles)."""
+    from tests.gpu_util import lowp_bars, round_like_storage
+    g = _geometry()
+    rng = np.random.default_rng(100 + C)
+    y = (rng.normal(size=(C, g.Q, g.M, g.K)) + 1j * rng.normal(size=(C, g.Q, g.M, g.K))).astype(np.complex64)
+    say(f"IQ mfma {form} {storage}, {C} complex items")
+    x, lanes = _run_mfma(g, y, 7.5e6, gpu, storage, form)
+    items = sorted({0, C // 2, C - 1})
+    _check_c(x[items], forward_iq(y[items], g, 7.5e6), *lowp_bars(storage), "raw data")
+    r = round_like_storage(lanes, storage)
+    yr = r[0::2] + 1j * r[1::2]
+    _check_c(x[items], forward_iq(yr[items], g, 7.5e6), *MFMA_KERNEL, "  rounded data")
+
+
+def test_iq_mfma_refuses_bf16(gpu):
+    das = _das()
+    g = _geometry()
+    p = das.Plan(g, max_batch=16, storage="bf16", algo="mfma")
+    p.set_iq(7.5e6)
+    with pytest.raises(das.DasError) as e:
+        p.forward(synth.random_channel_data(g, 16, seed=2).to(gpu))
+    assert e.value.status == das.DAS_ERR_UNSUPPORTED
