@@ -101,7 +101,8 @@ def recorded_traffic(kernel, tile):
     """HBM traffic per launch of `kernel` from the rocprofv3 FETCH_SIZE / WRITE_SIZE
     passes recorded in profiles/traffic.json (each scaled by what the counter reads
     for a plain copy of known size), or None when the kernel's sources have changed
-    since the counters were taken or they were taken with another tile shape."""
+    since the counters were taken or they were taken with another tile shape (for
+    the matrix-core form: another launch form)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -188,7 +189,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(frames or voxel slabs would shard with no communication; see DESIGN.md)",
+              "(frames or voxel slabs would shard with no communication)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -443,7 +444,8 @@ def run_ensemble(args, torch, np, das, synth, g, counts, forms, workers):
              "forward_ms": round(fwf, 4), "prepare_ms": round(prf, 4), "batch": B, "storage": st,
              "algo": pf.algo(B), "mfma_form": pf.mfma_form(), "per_frame_latency_ms": round(wf, 3),
              "data": note,
-             "roofline": mfma_roofline(counts, B, st, g, fwf)}
+             "roofline": mfma_roofline(counts, B, st, g, fwf,
+                                       recorded_traffic(f"mfma_forward {st} B={B}", [pf.mfma_form()]))}
         if xo is not None:
             xs = xf[check][:, idx_t].cpu().numpy()
             f["rel_l2_frames"] = {str(fr): float(np.linalg.norm(xs[i] - xo[i]) / np.linalg.norm(xo[i]))

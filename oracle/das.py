@@ -19,7 +19,7 @@ What is computed (paper, Sec. 2):
 * Channel data are batched as y[B, Q, M, K] (Sec. 2, last paragraphs); one
   output volume per batch item.
 
-Readings of what the paper leaves open (each is also listed in the design doc):
+Readings of what the paper leaves open:
 
 * R1 plane-wave sign: the descriptor is the propagation direction u (into the
   medium) and the transmit path is u.p, i.e. time zero is when the wavefront

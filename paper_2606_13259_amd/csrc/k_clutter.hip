@@ -9,20 +9,22 @@
 //   1. Gram matrix G = x x^T (T x T), the only O(N T^2) step: a dense
 //      contraction over voxels on the matrix cores (v_mfma_f32_16x16x4_f32,
 //      FP32 products and partial sums over one voxel chunk), chunks merged in
-//      FP64 with atomics.  Workgroups own a 64 x 64 block of G (upper
-//      triangle only) for one voxel chunk; the two 64-frame row panels of a
-//      64-voxel step are staged through LDS with coalesced loads.
+//      FP64 with atomics.  T <= 256: a workgroup forms the whole upper
+//      triangle for its voxel chunk from one LDS stage of all frames, so the
+//      ensemble is read once; larger T: workgroups own 64 x 64 blocks.
 //   2. Eigen-decomposition G = V diag(lambda) V^T in FP64: Householder
 //      tridiagonalisation (one workgroup, matrix in L2), all eigenvalues by
-//      multisection on Sturm counts (one wavefront each), eigenvectors by
-//      inverse iteration (one thread each) re-orthogonalised within
-//      clusters, back-transformed by the reflectors (one workgroup each).
-//      sigma = sqrt(lambda), sorted; the columns of V that the filter needs
-//      are copied (FP32) as the projection basis B.
+//      multisection on Sturm counts (one wavefront each), and the
+//      eigenvectors that the filter uses (at most 64) by inverse iteration
+//      in LDS, re-orthogonalised within clusters and back-transformed by the
+//      reflectors.  sigma = sqrt(lambda), sorted; those columns of V are
+//      the projection basis B (FP32 and FP64).
 //   3. Projection and power: per voxel, a = B^T s_n, then the filtered
 //      series is B a (keep form) or s_n - B a (removal form), whichever uses
-//      fewer components (at most 64), and P[n] its mean square.  Every voxel
-//      reads its T samples twice (from L2 or HBM); B sits in LDS.
+//      fewer components (at most 64), and P[n] its mean square.  When only
+//      the power is asked for (and the basis is small), one FP64 pass gives
+//      it from |a|^2 and |s_n|^2; otherwise every voxel reads its T samples
+//      twice (from L2 or HBM).  B sits in LDS.
 #include <mutex>
 
 #include "das_internal.h"
@@ -103,6 +105,113 @@ __global__ __launch_bounds__(256) void gram_mfma(const float* __restrict__ x, in
       }
 }
 
+// T <= 256: G[i][j] += sum over voxel chunk blockIdx.x (csz voxels) of
+// x[i][n] x[j][n] for the whole upper triangle, so that every sample is
+// staged once.  Stage: 32 voxels of all frames in LDS (rows padded to 36
+// floats: the 16-byte fragment reads of 16 rows fall in distinct banks).
+// The triangle is cut into 32 x 32 super-tiles (I, J), I <= J; wavefront w
+// owns super-rows w and 7 - w, nine super-tiles, each 2 x 2 MFMA tiles of
+// v_mfma_f32_16x16x4_f32.  A lane reads four consecutive voxels of its row
+// (one b128) and feeds them to four MFMAs: the contracted index of MFMA c is
+// voxel 4 (lane / 16) + c of the 16-voxel half-stage, the same for both
+// operands, so the sum runs over every voxel once.
+constexpr int kFullT = 256;
+constexpr int GF_KV = 32;
+constexpr int GF_PITCH = GF_KV + 4;
+
+__global__ __launch_bounds__(256) void gram_full(const float* __restrict__ x, int T, long long N,
+                                                 long long csz, double* __restrict__ G) {
+  __shared__ __attribute__((aligned(16))) float Xs[kFullT * GF_PITCH];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int ng = (T + 31) >> 5;  // super-rows
+  const int rows = 32 * ng;
+  const long long v0 = (long long)blockIdx.x * csz;
+  const long long v1 = min(N, v0 + csz);
+  const bool vec = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  f32x4 acc[9][2][2];
+#pragma unroll
+  for (int q = 0; q < 9; ++q)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) acc[q][u][v] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the next stage's samples are loaded into registers while the MFMAs of
+  // the current one run (one wavefront per SIMD: nothing else hides them)
+  constexpr int kQuads = kFullT * GF_KV / 4 / 256;  // 16-byte loads per thread
+  f32x4 pre[kQuads];
+  auto fetch = [&](long long s) {
+    const bool full = vec && s + GF_KV <= v1;
+#pragma unroll
+    for (int i = 0; i < kQuads; ++i) {
+      const int idx = t + 256 * i, r = idx >> 3, qd = idx & 7;
+      f32x4 val = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (r < T) {
+        const float* src = x + (long long)r * N + s + 4 * qd;
+        if (full) {
+          val = *reinterpret_cast<const f32x4*>(src);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (s + 4 * qd + c < v1) val[c] = src[c];
+        }
+      }
+      pre[i] = val;
+    }
+  };
+  if (v0 < v1) fetch(v0);
+  for (long long s = v0; s < v1; s += GF_KV) {
+    __syncthreads();  // the previous stage is no longer read
+#pragma unroll
+    for (int i = 0; i < kQuads; ++i) {
+      const int idx = t + 256 * i, r = idx >> 3, qd = idx & 7;
+      if (r < rows) *reinterpret_cast<f32x4*>(Xs + r * GF_PITCH + 4 * qd) = pre[i];
+    }
+    __syncthreads();
+    if (s + GF_KV < v1) fetch(s + GF_KV);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = 16 * h + 4 * (lane >> 4);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        // super-tile q of this wavefront
+        const int I = q <= 7 - wave ? wave : 7 - wave;
+        const int J = q <= 7 - wave ? wave + q : q - 1;
+        if (J >= ng) continue;  // uniform over the wavefront
+        f32x4 a[2], b[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          a[u] = *reinterpret_cast<const f32x4*>(Xs + (32 * I + 16 * u + (lane & 15)) * GF_PITCH + col);
+          b[u] = *reinterpret_cast<const f32x4*>(Xs + (32 * J + 16 * u + (lane & 15)) * GF_PITCH + col);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+              acc[q][u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][c], b[v][c], acc[q][u][v], 0, 0, 0);
+      }
+    }
+  }
+  // D of a tile: lane holds rows 4 (lane / 16) + r, column lane % 16
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const int I = q <= 7 - wave ? wave : 7 - wave;
+    const int J = q <= 7 - wave ? wave + q : q - 1;
+    if (J >= ng) continue;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 32 * I + 16 * u + 4 * (lane >> 4) + r;
+          const int j = 32 * J + 16 * v + (lane & 15);
+          if (j < T && i <= j) atomicAdd(G + (size_t)i * T + j, (double)acc[q][u][v][r]);
+        }
+  }
+}
+
 // A(i, j) of the symmetric matrix kept in the upper triangle of a.
 __device__ inline double& up(double* a, int T, int i, int j) {
   return i <= j ? a[(size_t)i * T + j] : a[(size_t)j * T + i];
@@ -131,9 +240,10 @@ __device__ inline double block_sum(double v, double* red) {
 //      working matrix lives in global memory and stays in L2);
 //   2. every eigenvalue of the tridiagonal matrix by multisection on Sturm
 //      counts (one wavefront per eigenvalue, 64 points per iteration);
-//   3. its eigenvectors by inverse iteration (one thread per vector, LU with
-//      partial pivoting of the shifted tridiagonal matrix), re-orthogonalised
-//      within clusters of (nearly) equal eigenvalues;
+//   3. the eigenvectors of the projection basis by inverse iteration (one
+//      wavefront per vector, LU with partial pivoting of the shifted
+//      tridiagonal matrix in LDS), re-orthogonalised within clusters of
+//      (nearly) equal eigenvalues;
 //   4. back-transformation V = Q Y (one workgroup per vector).
 // FP64 keeps every eigenvector accurate to ~1e-16 of the largest eigenvalue
 // over its gap, also for the weak components of a wide dynamic range.
@@ -144,8 +254,8 @@ __device__ inline double block_sum(double v, double* red) {
 __global__ __launch_bounds__(1024) void tri_reduce(const double* __restrict__ G, int T,
                                                    double* __restrict__ A, double* __restrict__ d,
                                                    double* __restrict__ e, double* __restrict__ tau) {
-  __shared__ double v[kMaxT], w[kMaxT], red[16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  __shared__ double v[kMaxT], w[kMaxT], pp[4 * kMaxT], red[16];
+  const int tid = threadIdx.x, col = tid & 255, part = tid >> 8;  // blockDim.x = 1024
   // G holds the upper triangle (the Gram kernel forms blocks I <= J)
   for (int w = tid; w < T * T; w += blockDim.x) {
     const int i = w / T, j = w - i * T;
@@ -172,24 +282,31 @@ __global__ __launch_bounds__(1024) void tri_reduce(const double* __restrict__ G,
     const double t = 1.0 / (alpha * (alpha - x0));  // 2 / (u^T u)
     if (tid < n) v[tid] = tid == 0 ? x0 - alpha : xi;
     __syncthreads();
-    // p = t B u (rows by wavefronts, columns by lanes), w = p - (t/2 u^T p) u
-    for (int i = wave; i < n; i += nw) {
-      const double* row = A + (size_t)(k + 1 + i) * T + (k + 1);
+    // p = t B u: B is symmetric, so p_c = sum_r B[r][c] u_r, thread (part,
+    // column c) summing a quarter of the rows; consecutive threads read
+    // consecutive columns of a row and the row loads are independent.
+    const int r0 = part * ((n + 3) >> 2), r1 = min(n, r0 + ((n + 3) >> 2));
+    for (int c = col; c < n; c += 256) {
+      const double* bc = A + (size_t)(k + 1) * T + (k + 1) + c;
       double acc = 0.0;
-      for (int j = lane; j < n; j += 64) acc += row[j] * v[j];
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-      if (lane == 0) w[i] = t * acc;
+#pragma unroll 4
+      for (int r = r0; r < r1; ++r) acc += bc[(size_t)r * T] * v[r];
+      pp[part * kMaxT + c] = acc;
     }
     __syncthreads();
+    if (tid < n) w[tid] = t * (pp[tid] + pp[kMaxT + tid] + pp[2 * kMaxT + tid] + pp[3 * kMaxT + tid]);
+    __syncthreads();
+    // w = p - (t/2 u^T p) u
     const double up_ = block_sum(tid < n ? v[tid] * w[tid] : 0.0, red);
     const double K = 0.5 * t * up_;
     if (tid < n) w[tid] -= K * v[tid];
     __syncthreads();
-    // B -= u w^T + w u^T
-    for (int i = wave; i < n; i += nw) {
-      double* row = A + (size_t)(k + 1 + i) * T + (k + 1);
-      const double vi = v[i], wi = w[i];
-      for (int j = lane; j < n; j += 64) row[j] -= vi * w[j] + wi * v[j];
+    // B -= u w^T + w u^T, same thread layout
+    for (int c = col; c < n; c += 256) {
+      double* bc = A + (size_t)(k + 1) * T + (k + 1) + c;
+      const double vc = v[c], wc = w[c];
+#pragma unroll 4
+      for (int r = r0; r < r1; ++r) bc[(size_t)r * T] -= v[r] * wc + w[r] * vc;
     }
     if (tid == 0) {
       d[k] = A[(size_t)k * T + k];
@@ -263,25 +380,41 @@ __global__ __launch_bounds__(64) void tri_bisect(const double* __restrict__ d,
   if (lane == 0) lam[i] = 0.5 * (lo + hi);
 }
 
-// 3. Inverse iteration, one thread per eigenvector j: Gaussian elimination
-// with partial pivoting of tridiag(e, d - lam_j, e) (U with two
-// superdiagonals, multipliers and row-swap flags in sc[5][T][T], component-
-// major so that the threads of a wavefront touch consecutive addresses),
-// then three solves from a fixed pseudo-random start, each normalised.
-// Y[t][j] = component t of eigenvector j.
+// Rank of eigenvalue i in descending order, ties by index (the order the
+// filter's component numbers k_lo, k_hi refer to).
+__device__ inline int descending_rank(const double* lam, int T, int i) {
+  const double li = lam[i];
+  int rk = 0;
+  for (int j = 0; j < T; ++j) {
+    const double lj = lam[j];
+    rk += (lj > li) || (lj == li && j < i);
+  }
+  return rk;
+}
+
+// Whether eigenvalue i's eigenvector enters the projection basis: the
+// components k_lo .. k_hi-1 (keep form) or the others (removal form).
+__device__ inline bool in_projection_basis(const double* lam, int T, int i, int k_lo, int k_hi,
+                                           int keep) {
+  const int rk = descending_rank(lam, T, i);
+  const bool band = rk >= k_lo && rk < k_hi;
+  return keep ? band : !band;
+}
+
+// 3. Inverse iteration for the eigenvectors of the projection basis (the
+// others are never used), one workgroup of one wavefront per eigenvector j
+// with lane 0 doing the serial work in LDS: Gaussian elimination with
+// partial pivoting of tridiag(e, d, e) - lam_j I (U with two
+// superdiagonals, multipliers and row-swap flags), then three solves from a
+// fixed pseudo-random start, each normalised.  Y[t][j] = component t.
 __global__ __launch_bounds__(64) void tri_inverse(const double* __restrict__ d,
                                                   const double* __restrict__ e,
-                                                  const double* __restrict__ lam, int T,
-                                                  double* __restrict__ sc, double* __restrict__ Y) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= T) return;
-  const size_t TT = (size_t)T * T;
-  double* U0 = sc;
-  double* U1 = sc + TT;
-  double* U2 = sc + 2 * TT;
-  double* L = sc + 3 * TT;
-  double* P = sc + 4 * TT;
-  auto at = [&](double* arr, int t) -> double& { return arr[(size_t)t * T + j]; };
+                                                  const double* __restrict__ lam, int T, int k_lo,
+                                                  int k_hi, int keep, double* __restrict__ Y) {
+  __shared__ double U0[kMaxT], U1[kMaxT], U2[kMaxT], L[kMaxT], y[kMaxT];
+  __shared__ unsigned char P[kMaxT];
+  const int j = blockIdx.x;
+  if (threadIdx.x != 0 || !in_projection_basis(lam, T, j, k_lo, k_hi, keep)) return;
   double anorm = 0.0;
   for (int t = 0; t < T; ++t)
     anorm = fmax(anorm, fabs(d[t]) + (t > 0 ? fabs(e[t - 1]) : 0.0) + (t + 1 < T ? fabs(e[t]) : 0.0));
@@ -294,72 +427,78 @@ __global__ __launch_bounds__(64) void tri_inverse(const double* __restrict__ d,
     const double sub = e[t], na = d[t + 1] - lj, nb = t + 2 < T ? e[t + 1] : 0.0;
     if (fabs(sub) > fabs(a)) {  // swap: the next row is the pivot row
       const double m = a / sub;
-      at(U0, t) = sub;
-      at(U1, t) = na;
-      at(U2, t) = nb;
-      at(L, t) = m;
-      at(P, t) = 1.0;
+      U0[t] = sub;
+      U1[t] = na;
+      U2[t] = nb;
+      L[t] = m;
+      P[t] = 1;
       a = b - m * na;
       b = -m * nb;
     } else {
       if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
       const double m = sub / a;
-      at(U0, t) = a;
-      at(U1, t) = b;
-      at(U2, t) = 0.0;
-      at(L, t) = m;
-      at(P, t) = 0.0;
+      U0[t] = a;
+      U1[t] = b;
+      U2[t] = 0.0;
+      L[t] = m;
+      P[t] = 0;
       a = na - m * b;
       b = nb;
     }
   }
   if (fabs(a) < tiny) a = a < 0.0 ? -tiny : tiny;
-  at(U0, T - 1) = a;
-  at(U1, T - 1) = 0.0;
-  at(U2, T - 1) = 0.0;
+  U0[T - 1] = a;
+  U1[T - 1] = 0.0;
+  U2[T - 1] = 0.0;
   // start vector
   for (int t = 0; t < T; ++t) {
     const uint32_t h = (uint32_t)t * 2654435761u ^ ((uint32_t)j * 40503u + 0x9e3779b9u);
-    at(Y, t) = 0.5 + (double)((h >> 8) & 0xffff) / 65536.0;
+    y[t] = 0.5 + (double)((h >> 8) & 0xffff) / 65536.0;
   }
   for (int it = 0; it < 3; ++it) {
     // forward: apply the row operations to the right-hand side (in place)
-    double r = at(Y, 0);
+    double r = y[0];
     for (int t = 0; t + 1 < T; ++t) {
-      const double y1 = at(Y, t + 1), m = at(L, t);
-      if (at(P, t) != 0.0) {
-        at(Y, t) = y1;
+      const double y1 = y[t + 1], m = L[t];
+      if (P[t]) {
+        y[t] = y1;
         r = r - m * y1;
       } else {
-        at(Y, t) = r;
+        y[t] = r;
         r = y1 - m * r;
       }
     }
-    at(Y, T - 1) = r;
+    y[T - 1] = r;
     // back substitution
-    double x2 = 0.0, x1 = at(Y, T - 1) / at(U0, T - 1);
-    at(Y, T - 1) = x1;
+    double x2 = 0.0, x1 = y[T - 1] / U0[T - 1];
+    y[T - 1] = x1;
     double nrm = x1 * x1;
     for (int t = T - 2; t >= 0; --t) {
-      const double x = (at(Y, t) - at(U1, t) * x1 - at(U2, t) * x2) / at(U0, t);
-      at(Y, t) = x;
+      const double x = (y[t] - U1[t] * x1 - U2[t] * x2) / U0[t];
+      y[t] = x;
       nrm += x * x;
       x2 = x1;
       x1 = x;
     }
     const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-    for (int t = 0; t < T; ++t) at(Y, t) *= inv;
+    for (int t = 0; t < T; ++t) y[t] *= inv;
   }
+  for (int t = 0; t < T; ++t) Y[(size_t)t * T + j] = y[t];
 }
 
-// 3b. Re-orthogonalise eigenvectors within clusters of eigenvalues closer
-// than 1e-9 of the spectral radius (inverse iteration leaves vectors of
-// (nearly) equal eigenvalues non-orthogonal), by classical Gram-Schmidt
-// applied twice, in ascending order; one workgroup.
-__global__ __launch_bounds__(1024) void tri_orth(const double* __restrict__ lam, int T,
-                                                 double* __restrict__ Y) {
+// 3b. Re-orthogonalise, within clusters of eigenvalues closer than 1e-9 of
+// the spectral radius, the eigenvectors that enter the projection basis
+// (inverse iteration leaves vectors of (nearly) equal eigenvalues
+// non-orthogonal): classical Gram-Schmidt applied twice, in ascending order,
+// each basis vector against the cluster's earlier basis vectors.  The other
+// eigenvectors are never used, so they are left as they are; one workgroup.
+__global__ __launch_bounds__(1024) void tri_orth(const double* __restrict__ lam, int T, int k_lo,
+                                                 int k_hi, int keep, double* __restrict__ Y) {
   __shared__ double dots[kMaxT], red[16];
+  __shared__ int in_basis[kMaxT];
   const int tid = threadIdx.x;
+  for (int i = tid; i < T; i += blockDim.x) in_basis[i] = in_projection_basis(lam, T, i, k_lo, k_hi, keep);
+  __syncthreads();
   double lmax = 0.0;
   for (int j = 0; j < T; ++j) lmax = fmax(lmax, fabs(lam[j]));
   const double tol = 1e-9 * lmax;
@@ -369,17 +508,20 @@ __global__ __launch_bounds__(1024) void tri_orth(const double* __restrict__ lam,
       cs = j;
       continue;
     }
+    if (!in_basis[j]) continue;  // uniform over the workgroup
     for (int pass = 0; pass < 2; ++pass) {
-      // dots with the cluster's previous vectors (one thread each)
+      // dots with the cluster's earlier basis vectors (one thread each)
       for (int i = cs + tid; i < j; i += blockDim.x) {
         double acc = 0.0;
-        for (int t = 0; t < T; ++t) acc += Y[(size_t)t * T + i] * Y[(size_t)t * T + j];
+        if (in_basis[i])  // other columns of Y are not formed
+          for (int t = 0; t < T; ++t) acc += Y[(size_t)t * T + i] * Y[(size_t)t * T + j];
         dots[i] = acc;
       }
       __syncthreads();
       for (int t = tid; t < T; t += blockDim.x) {
         double y = Y[(size_t)t * T + j];
-        for (int i = cs; i < j; ++i) y -= dots[i] * Y[(size_t)t * T + i];
+        for (int i = cs; i < j; ++i)
+          if (in_basis[i]) y -= dots[i] * Y[(size_t)t * T + i];
         Y[(size_t)t * T + j] = y;
       }
       __syncthreads();
@@ -393,14 +535,16 @@ __global__ __launch_bounds__(1024) void tri_orth(const double* __restrict__ lam,
   }
 }
 
-// 4. V = Q Y, one workgroup per eigenvector j: the Householder reflectors
-// H_{T-3} .. H_0 applied in turn.
+// 4. V = Q Y for the basis eigenvectors, one workgroup per eigenvector j:
+// the Householder reflectors H_{T-3} .. H_0 applied in turn.
 __global__ __launch_bounds__(256) void tri_back(const double* __restrict__ A,
                                                 const double* __restrict__ tau,
                                                 const double* __restrict__ Y,
-                                                int T, double* __restrict__ V) {
+                                                const double* __restrict__ lam, int T, int k_lo,
+                                                int k_hi, int keep, double* __restrict__ V) {
   __shared__ double y[kMaxT], red[16];
   const int j = blockIdx.x, tid = threadIdx.x;
+  if (!in_projection_basis(lam, T, j, k_lo, k_hi, keep)) return;  // uniform
   for (int t = tid; t < T; t += blockDim.x) y[t] = Y[(size_t)t * T + j];
   __syncthreads();
   for (int k = T - 3; k >= 0; --k) {
@@ -417,29 +561,27 @@ __global__ __launch_bounds__(256) void tri_back(const double* __restrict__ A,
 }
 
 // Rank the eigenvalues (descending, ties by index), write sigma = sqrt(lambda),
-// and copy the projection basis B[T][nb] (FP32): the eigenvectors of ranks
-// [k_lo, k_hi) for the keep form, the others for the removal form.
+// and copy the projection basis B[T][nb] (FP32 and FP64): the eigenvectors of
+// ranks [k_lo, k_hi) for the keep form, the others for the removal form.
 __global__ __launch_bounds__(1024) void rank_basis(const double* __restrict__ lam,
                                                    const double* __restrict__ v, int T, int k_lo,
                                                    int k_hi, int keep, float* __restrict__ sv,
-                                                   float* __restrict__ Bm, int nb) {
+                                                   float* __restrict__ Bm, double* __restrict__ Bd,
+                                                   int nb) {
   __shared__ int rank_of[kMaxT];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < T; i += nt) {
-    const double li = lam[i];
-    int rk = 0;
-    for (int j = 0; j < T; ++j) {
-      const double lj = lam[j];
-      rk += (lj > li) || (lj == li && j < i);
-    }
+    const int rk = descending_rank(lam, T, i);
     rank_of[rk] = i;
-    sv[rk] = (float)sqrt(fmax(li, 0.0));
+    sv[rk] = (float)sqrt(fmax(lam[i], 0.0));
   }
   __syncthreads();
   for (int w = tid; w < T * nb; w += nt) {
     const int t = w / nb, j = w - t * nb;
     const int rk = keep ? k_lo + j : (j < k_lo ? j : k_hi + (j - k_lo));
-    Bm[w] = (float)v[(size_t)t * T + rank_of[rk]];
+    const double b = v[(size_t)t * T + rank_of[rk]];
+    Bm[w] = (float)b;
+    Bd[w] = b;
   }
 }
 
@@ -479,6 +621,47 @@ __global__ __launch_bounds__(256) void project_power(const float* __restrict__ x
   pd[n] = (float)(pw / T);
 }
 
+// Power only (no filtered series): with B orthonormal, a = B^T s_n carries
+// the kept energy |a|^2 (keep form), and the removal form keeps
+// |s_n|^2 - |a|^2; both in FP64 with the FP64 basis, so the difference is
+// exact to far below the FP32 output even when the removed clutter is many
+// orders above the rest.  One read of the series.  NBMAX >= nb.
+template <int NBMAX>
+__global__ __launch_bounds__(256) void power_1pass(const float* __restrict__ x, int T, long long N,
+                                                   const double* __restrict__ Bd, int nb, int keep,
+                                                   float* __restrict__ pd) {
+  extern __shared__ double Bs64[];
+  for (int i = threadIdx.x; i < T * nb; i += blockDim.x) Bs64[i] = Bd[i];
+  __syncthreads();
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  double a[NBMAX];
+#pragma unroll
+  for (int j = 0; j < NBMAX; ++j) a[j] = 0.0;
+  double ss = 0.0;
+  for (int t = 0; t < T; ++t) {
+    const double sv = (double)x[(long long)t * N + n];
+    ss = fma(sv, sv, ss);
+#pragma unroll
+    for (int j = 0; j < NBMAX; ++j)
+      if (j < nb) a[j] = fma(sv, Bs64[t * nb + j], a[j]);
+  }
+  double aa = 0.0;
+#pragma unroll
+  for (int j = 0; j < NBMAX; ++j) aa = fma(a[j], a[j], aa);
+  const double p = keep ? aa : fmax(ss - aa, 0.0);
+  pd[n] = (float)(p / T);
+}
+
+template <int NBMAX>
+hipError_t launch_power_1pass(const float* x, int T, long long N, const double* Bd, int nb, int keep,
+                              float* pd, hipStream_t st) {
+  const size_t lds = sizeof(double) * (size_t)T * nb;
+  hipLaunchKernelGGL(power_1pass<NBMAX>, dim3((unsigned)((N + 255) / 256)), dim3(256), lds, st, x, T,
+                     N, Bd, nb, keep, pd);
+  return hipGetLastError();
+}
+
 template <int NBMAX>
 hipError_t launch_project(const float* x, int T, long long N, const float* Bm, int nb, int keep,
                           float* pd, float* xf, hipStream_t st) {
@@ -497,10 +680,10 @@ hipError_t launch_project(const float* x, int T, long long N, const float* Bm, i
 constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Workspace layout (bytes from the start), every part 256-byte aligned:
-// G, V, A, Y (T x T f64 each), sc (5 T x T f64: the tridiagonal factors),
-// Bm (T x 64 f32), d, e, tau, lam (T f64 each).
+// G, V, A, Y (T x T f64 each), Bm (T x 64 f32), Bd (T x 64 f64), d, e, tau,
+// lam (T f64 each).
 struct ClutterWs {
-  size_t G, V, A, Y, sc, Bm, d, e, tau, lam, total;
+  size_t G, V, A, Y, Bm, Bd, d, e, tau, lam, total;
 };
 constexpr ClutterWs ws_layout(int T) {
   const size_t tt = align256(sizeof(double) * (size_t)T * T), t8 = align256(sizeof(double) * (size_t)T);
@@ -510,8 +693,8 @@ constexpr ClutterWs ws_layout(int T) {
   L.V = o; o += tt;
   L.A = o; o += tt;
   L.Y = o; o += tt;
-  L.sc = o; o += 5 * tt;
   L.Bm = o; o += align256(sizeof(float) * (size_t)T * 64);
+  L.Bd = o; o += align256(sizeof(double) * (size_t)T * 64);
   L.d = o; o += t8;
   L.e = o; o += t8;
   L.tau = o; o += t8;
@@ -522,7 +705,7 @@ constexpr ClutterWs ws_layout(int T) {
 constexpr size_t workspace_bytes(int T) { return ws_layout(T).total; }
 
 // Workspace of the allocation-free entry point: room for ensembles of up to
-// kStaticT frames (4.6 MiB), one copy per device, held until the process
+// kStaticT frames (2.2 MiB), one copy per device, held until the process
 // ends.  In host code `scratch` names a host-side stand-in, not the device
 // array: its device address comes from hipGetSymbolAddress, once per device.
 constexpr int kStaticT = 256;
@@ -570,8 +753,8 @@ hipError_t launch_clutter_filter(const float* x, int T, long long N, int k_lo, i
   double* V = reinterpret_cast<double*>(w + L.V);
   double* A = reinterpret_cast<double*>(w + L.A);
   double* Y = reinterpret_cast<double*>(w + L.Y);
-  double* sc = reinterpret_cast<double*>(w + L.sc);
   float* Bm = reinterpret_cast<float*>(w + L.Bm);
+  double* Bd = reinterpret_cast<double*>(w + L.Bd);
   double* d = reinterpret_cast<double*>(w + L.d);
   double* e_ = reinterpret_cast<double*>(w + L.e);
   double* tau = reinterpret_cast<double*>(w + L.tau);
@@ -582,26 +765,41 @@ hipError_t launch_clutter_filter(const float* x, int T, long long N, int k_lo, i
   hipLaunchKernelGGL(zero_f64, dim3(256), dim3(256), 0, st, G, (size_t)T * T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int nbk = (T + GB - 1) / GB, npairs = nbk * (nbk + 1) / 2;
-  const long long nsteps = (N + GB - 1) / GB;
-  const long long nchunk = std::max(1LL, std::min(nsteps, (long long)(8 * cus) / npairs + 1));
-  const long long csz = (nsteps + nchunk - 1) / nchunk * GB;
-  const long long nch = (N + csz - 1) / csz;
-  hipLaunchKernelGGL(gram_mfma, dim3((unsigned)npairs, (unsigned)nch), dim3(256), 0, st, x, T, N,
-                     csz, nbk, G);
+  if (T <= kFullT) {
+    // two workgroups per CU, each a whole number of 32-voxel stages
+    const long long nstage = (N + GF_KV - 1) / GF_KV;
+    const long long nwg = std::max(1LL, std::min(nstage, 2LL * cus));
+    const long long csz = (nstage + nwg - 1) / nwg * GF_KV;
+    const long long nch = (N + csz - 1) / csz;
+    hipLaunchKernelGGL(gram_full, dim3((unsigned)nch), dim3(256), 0, st, x, T, N, csz, G);
+  } else {
+    const int nbk = (T + GB - 1) / GB, npairs = nbk * (nbk + 1) / 2;
+    const long long nsteps = (N + GB - 1) / GB;
+    const long long nchunk = std::max(1LL, std::min(nsteps, (long long)(8 * cus) / npairs + 1));
+    const long long csz = (nsteps + nchunk - 1) / nchunk * GB;
+    const long long nch = (N + csz - 1) / csz;
+    hipLaunchKernelGGL(gram_mfma, dim3((unsigned)npairs, (unsigned)nch), dim3(256), 0, st, x, T, N,
+                       csz, nbk, G);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(tri_reduce, dim3(1), dim3(1024), 0, st, G, T, A, d, e_, tau);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(tri_bisect, dim3(T), dim3(64), 0, st, d, e_, T, lam);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(tri_inverse, dim3((T + 63) / 64), dim3(64), 0, st, d, e_, lam, T, sc, Y);
+  hipLaunchKernelGGL(tri_inverse, dim3(T), dim3(64), 0, st, d, e_, lam, T, k_lo, k_hi, keep, Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(tri_orth, dim3(1), dim3(1024), 0, st, lam, T, Y);
+  hipLaunchKernelGGL(tri_orth, dim3(1), dim3(1024), 0, st, lam, T, k_lo, k_hi, keep, Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(tri_back, dim3(T), dim3(256), 0, st, A, tau, Y, T, V);
+  hipLaunchKernelGGL(tri_back, dim3(T), dim3(256), 0, st, A, tau, Y, lam, T, k_lo, k_hi, keep, V);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(rank_basis, dim3(1), dim3(1024), 0, st, lam, V, T, k_lo, k_hi, keep, sv, Bm, nb);
+  hipLaunchKernelGGL(rank_basis, dim3(1), dim3(1024), 0, st, lam, V, T, k_lo, k_hi, keep, sv, Bm, Bd,
+                     nb);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!xf && nb > 0 && nb <= 16 && sizeof(double) * (size_t)T * nb <= 48 * 1024) {
+    if (nb <= 4) return launch_power_1pass<4>(x, T, N, Bd, nb, keep, pd, st);
+    if (nb <= 8) return launch_power_1pass<8>(x, T, N, Bd, nb, keep, pd, st);
+    return launch_power_1pass<16>(x, T, N, Bd, nb, keep, pd, st);
+  }
   if (nb == 0) {  // keep nothing or remove nothing
     return launch_project<1>(x, T, N, Bm, 0, keep, pd, xf, st);
   }

@@ -2,22 +2,20 @@
 the FP64 oracle (oracle.clutter).
 
 Bars (derived from the arithmetic): the Gram matrix is formed from FP32
-products summed in FP32 over one voxel chunk (at most a few thousand
-64-voxel steps) and in FP64 across chunks, a relative error of order 1e-6 of
-its largest entry; the FP64 Jacobi adds nothing comparable.  By Weyl's
-inequality every eigenvalue sigma_i^2 is then within that error of
-sigma_1^2: bar |sigma_i^2 - sigma_o,i^2| <= 2e-5 sigma_1^2.  The filtered
-series depends on the kept subspace, whose angle error is the Gram error over
-the gap at the cut (the test ensembles have clear gaps there), and on FP32
-rounding of the removal form s - B a (relative 1e-7 of the clutter
-amplitude): bar rel-L2 <= 1e-4 on the power image.  For T <= 256 the
-eigen-solve runs in FP32 (in LDS) followed by one first-order FP64
-correction across the cuts, which leaves a rotation of order
-(2^-24 sigma_1^2 / gap)^2 at a cut: up to ~4e-3 at the noise-tail cut of the
-band test (sigma_1^2 = 1e6, gap ~1), weighted by that component's small
-share of the kept energy; the filtered series has the bar 1e-3.  Singular
-vectors have arbitrary signs, so only the singular values, the power image
-and the filtered series (all unique) are compared."""
+products summed in FP32 over one voxel chunk (a few thousand voxels) and in
+FP64 across chunks, a relative error of order 1e-6 of its largest entry;
+the FP64 eigen-solve (Householder, Sturm multisection, inverse iteration)
+adds nothing comparable.  By Weyl's inequality every eigenvalue sigma_i^2 is
+then within that error of sigma_1^2: bar |sigma_i^2 - sigma_o,i^2| <= 2e-5
+sigma_1^2.  The filtered series depends on the kept subspace, whose angle
+error is the Gram error over the gap at the cut (the test ensembles have
+clear gaps there), and on FP32 rounding of the removal form s - B a
+(relative 1e-7 of the clutter amplitude): bar rel-L2 <= 1e-4 on the power
+image, 1e-3 on the filtered series.  The power alone (no filtered series,
+small basis) is formed in one FP64 pass as |s|^2 - |a|^2 (removal form) or
+|a|^2 (keep form), under the same bar.  Singular vectors have arbitrary
+signs, so only the singular values, the power image and the filtered series
+(all unique) are compared."""
 import numpy as np
 import pytest
 import torch
@@ -64,6 +62,14 @@ def _check(x, k_lo, k_hi, gpu, what, filtered=True):
         e_xf = float(np.linalg.norm(xg - xo) / (no if no > 1e-3 * nx else nx))
         say(f"    filtered series rel-L2 {e_xf:.2e} (bar {XF_BAR:g})")
         assert e_xf <= XF_BAR
+        # the power alone takes another route when the basis is small (one
+        # FP64 pass, |s|^2 - |a|^2): same bars
+        sv1, pw1, _ = das.clutter_filter(torch.from_numpy(x).to(gpu), k_lo, k_hi, filtered=False)
+        pw1 = pw1.cpu().numpy().reshape(-1).astype(np.float64)
+        e_pw1 = float(np.linalg.norm(pw1 - po) / den)
+        say(f"    power without the filtered series: rel-L2 {e_pw1:.2e} (bar {POWER_BAR:g})")
+        assert torch.equal(sv1.cpu(), torch.from_numpy(sv.astype(np.float32)))
+        assert e_pw1 <= POWER_BAR
     return sv, pw
 
 
