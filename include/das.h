@@ -304,8 +304,11 @@ das_status das_debug_delays(das_plan p, int32_t q, int32_t m0, int32_t m1, int32
  * otherwise; DAS_ERR_INVALID_ARG for bad sizes or NULL pointers).
  * Method: Gram matrix x x^T on the matrix cores (FP32, chunks merged in
  * FP64); FP64 eigen-decomposition (Householder tridiagonalisation,
- * multisection for the eigenvalues, inverse iteration for the eigenvectors,
- * back-transformation); per-voxel projection.
+ * multisection for the eigenvalues, inverse iteration and
+ * back-transformation for the eigenvectors of the projection basis: the kept
+ * components or the removed ones, whichever are fewer); per-voxel
+ * projection (power alone in one FP64 pass when xf is NULL and the basis
+ * has at most 16 vectors).
  * Runs on the calling thread's current device. */
 das_status das_clutter_workspace_bytes(int32_t T, size_t* bytes);
 das_status das_clutter_filter(const float* x, int32_t T, int64_t N, int32_t k_lo, int32_t k_hi,
@@ -314,7 +317,7 @@ das_status das_clutter_filter(const float* x, int32_t T, int64_t N, int32_t k_lo
 /* das_clutter_filter for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same computation with its workspace in a buffer the
- * library holds, a static device array of 4.6 MiB per device that lives
+ * library holds, a static device array of 2.2 MiB per device that lives
  * until the process ends.  No allocation of any kind is made.  Arguments as
  * for das_clutter_filter without ws; T <= 256 (DAS_ERR_INVALID_ARG above).
  * Every call on a device shares that device's buffer: calls that overlap on
