@@ -181,7 +181,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-sparse-tx", dest="sparse_tx", action="store_false",
                     help="skip the spatially selective transmit-weight forms")
-    ap.add_argument("--no-iq", dest="iq", action="store_false", help="skip the complex baseband form")
+    ap.add_argument("--no-iq", dest="iq", action="store_false", help="skip the complex baseband forms")
+    ap.add_argument("--no-cubic", dest="cubic", action="store_false",
+                    help="skip the cubic-interpolation form")
     ap.add_argument("--tile", type=int, default=None,
                     help="use this tile shape index instead of autotuning (profiling runs)")
     args = ap.parse_args()
@@ -267,13 +269,17 @@ def main():
     forms = {}
 
     def run_form(name, storage, algo, yb, steps, note=None, w_tx=None, iq_fc=None, roof=None,
-                 check=True):
+                 check=True, interp=None, mfma_form=None):
         B = yb.shape[0]
         pf = das.Plan(g, max_batch=B, storage=storage, algo=algo)
         if pf.algo(B) == "tiled":
             pf.set_tile(plan.tile())
+        elif mfma_form is not None:
+            pf.set_mfma_form(mfma_form)
         elif pf.algo(B) == "mfma":
             pf.autotune(B)
+        if interp is not None:
+            pf.set_interp(interp)
         if w_tx is not None:
             pf.set_tx_weights(w_tx)
         if iq_fc is not None:
@@ -306,6 +312,12 @@ def main():
         del_x = run_form(f"f32_plain_b{pb}", "f32", "plain", yb, 3, roof="valu",
                          note=None if pb == 1 else "the simulated frame repeated")
         del del_x, yb
+    # Four-point Lagrange (cubic) interpolation instead of the linear taps of
+    # Eq. (2), the windowed FP32 kernel (its oracle parity is in the GPU tests).
+    if args.cubic:
+        del_x = run_form("f32_cubic_b1", "f32", "tiled", y, max(3, args.steps // 2), check=False,
+                         interp="cubic", note="cubic interpolation of the simulated frame")
+        del del_x
     if args.sparse_tx:
         # A spatially selective transmit sequence (each transmit weighs one
         # lateral cell of a 4 x 4 layout, widened and tapered, zero elsewhere):
@@ -333,7 +345,15 @@ def main():
                       "per step (batch = the I and Q records)")
         forms["f32_iq_b1"]["volumes_per_s"] = round(forms["f32_iq_b1"]["volumes_per_s"] / 2, 2)
         forms["f32_iq_b1"]["unit_note"] = "complex volumes/s"
-        del za, yiq
+        # the same complex frame, 8 times, on the matrix cores (f16 storage,
+        # column launch: the IQ form is built for the column and slab launches)
+        yiq8 = yiq.repeat(8, 1, 1, 1).contiguous()
+        run_form("f16_iq_mfma_b16", "f16", "mfma", yiq8, max(2, args.steps // 4), iq_fc=7.5e6,
+                 check=False, mfma_form="column",
+                 note="IQ: the demodulated frame repeated; 8 complex volumes per step (16 items)")
+        forms["f16_iq_mfma_b16"]["volumes_per_s"] = round(forms["f16_iq_mfma_b16"]["volumes_per_s"] / 2, 2)
+        forms["f16_iq_mfma_b16"]["unit_note"] = "complex volumes/s"
+        del za, yiq, yiq8
     if args.batched > 1:
         B = args.batched
         yb = y.expand(B, -1, -1, -1).contiguous()

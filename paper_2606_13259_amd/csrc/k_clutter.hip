@@ -251,71 +251,145 @@ __device__ inline double block_sum(double v, double* red) {
 // 1. A: working copy of G (full, row-major, mirrored from the upper triangle
 // that the Gram kernel forms); on return column k below the diagonal holds
 // the Householder vector u_k (entries k+1 .. T-1).
+//
+// Blocked by panels of kPanel columns: within a panel the trailing matrix is
+// not touched; column k and the product B u_k are corrected on the fly for
+// the panel's earlier reflectors (B_cur = B - V W^T - W V^T, with V the
+// panel's Householder vectors and W the vectors w_k of their symmetric rank-2
+// updates), and the whole trailing matrix takes one rank-2 kPanel update at
+// the end of the panel: one read and write of it per panel instead of per
+// column.  V and W live in LDS (dynamic, 2 T kPanel doubles).  Threads:
+// (row quarter, column) for the matrix passes, so consecutive threads read
+// consecutive addresses of a row; B is symmetric, so p_c = sum_r B[r][c] u_r.
+constexpr int kPanel = 8;
+
 __global__ __launch_bounds__(1024) void tri_reduce(const double* __restrict__ G, int T,
                                                    double* __restrict__ A, double* __restrict__ d,
                                                    double* __restrict__ e, double* __restrict__ tau) {
-  __shared__ double v[kMaxT], w[kMaxT], pp[4 * kMaxT], red[16];
+  extern __shared__ double panel[];  // Vp[T][kPanel], Wp[T][kPanel]
+  __shared__ double u[kMaxT], wv[kMaxT], pp[4 * kMaxT], red[16], ycor[2 * kPanel * 2], x0s;
+  double* Vp = panel;
+  double* Wp = panel + (size_t)T * kPanel;
   const int tid = threadIdx.x, col = tid & 255, part = tid >> 8;  // blockDim.x = 1024
   // G holds the upper triangle (the Gram kernel forms blocks I <= J)
   for (int w = tid; w < T * T; w += blockDim.x) {
     const int i = w / T, j = w - i * T;
     A[w] = i <= j ? G[w] : G[(size_t)j * T + i];
   }
-  __syncthreads();
-  for (int k = 0; k + 2 < T; ++k) {
-    const int n = T - k - 1;  // the trailing block is rows / columns k+1 .. T-1
-    const double xi = tid < n ? A[(size_t)(k + 1 + tid) * T + k] : 0.0;
-    const double ss = block_sum(xi * xi, red);
-    const double x0 = A[(size_t)(k + 1) * T + k];
-    const double tail = ss - x0 * x0;
-    if (tail <= 1e-300 * fmax(ss, 1e-300) || ss == 0.0) {
-      // column already reduced: H_k = I
+  for (int k0 = 0; k0 + 2 < T;) {
+    const int npn = min(kPanel, T - 2 - k0);
+    __syncthreads();  // A mirrored / the previous panel's update no longer reads V, W
+    for (int w = tid; w < 2 * T * kPanel; w += blockDim.x) panel[w] = 0.0;
+    __syncthreads();  // panel cleared; the previous update's writes to A done
+    for (int i = 0; i < npn; ++i) {
+      const int k = k0 + i;
+      const int n = T - k - 1;  // the trailing block is rows / columns k+1 .. T-1
+      // column k, rows k .. T-1, with the panel's earlier reflectors applied
+      double a = 0.0;
+      if (tid <= n) {
+        const int r = k + tid;
+        a = A[(size_t)r * T + k];
+        for (int j = 0; j < i; ++j)
+          a -= Vp[r * kPanel + j] * Wp[k * kPanel + j] + Wp[r * kPanel + j] * Vp[k * kPanel + j];
+        if (tid >= 1) u[tid - 1] = a;
+        if (tid == 1) x0s = a;  // its own slot: thread 0 rewrites u[0] below
+      }
+      const double ss = block_sum(tid >= 1 && tid <= n ? a * a : 0.0, red);  // u, x0s visible after
+      const double x0 = x0s;
+      const double tail = ss - x0 * x0;
+      if (tail <= 1e-300 * fmax(ss, 1e-300) || ss == 0.0) {
+        // column already reduced: H_k = I (its V and W columns stay zero)
+        if (tid == 0) {
+          d[k] = a;
+          e[k] = x0;
+          tau[k] = 0.0;
+        }
+        __syncthreads();
+        continue;
+      }
+      const double alpha = x0 >= 0.0 ? -sqrt(ss) : sqrt(ss);
+      const double t = 1.0 / (alpha * (alpha - x0));  // 2 / (u^T u)
       if (tid == 0) {
-        d[k] = A[(size_t)k * T + k];
-        e[k] = x0;
-        tau[k] = 0.0;
+        u[0] = x0 - alpha;
+        d[k] = a;
+        e[k] = alpha;
+        tau[k] = t;
       }
       __syncthreads();
-      continue;
-    }
-    const double alpha = x0 >= 0.0 ? -sqrt(ss) : sqrt(ss);
-    const double t = 1.0 / (alpha * (alpha - x0));  // 2 / (u^T u)
-    if (tid < n) v[tid] = tid == 0 ? x0 - alpha : xi;
-    __syncthreads();
-    // p = t B u: B is symmetric, so p_c = sum_r B[r][c] u_r, thread (part,
-    // column c) summing a quarter of the rows; consecutive threads read
-    // consecutive columns of a row and the row loads are independent.
-    const int r0 = part * ((n + 3) >> 2), r1 = min(n, r0 + ((n + 3) >> 2));
-    for (int c = col; c < n; c += 256) {
-      const double* bc = A + (size_t)(k + 1) * T + (k + 1) + c;
-      double acc = 0.0;
+      // B u with the trailing matrix as it stood at the panel's start
+      const int r0 = part * ((n + 3) >> 2), r1 = min(n, r0 + ((n + 3) >> 2));
+      for (int c = col; c < n; c += 256) {
+        const double* bc = A + (size_t)(k + 1) * T + (k + 1) + c;
+        double acc = 0.0;
 #pragma unroll 4
-      for (int r = r0; r < r1; ++r) acc += bc[(size_t)r * T] * v[r];
-      pp[part * kMaxT + c] = acc;
+        for (int r = r0; r < r1; ++r) acc += bc[(size_t)r * T] * u[r];
+        pp[part * kMaxT + c] = acc;
+      }
+      // y1 = W^T u, y2 = V^T u over rows k+1 .. T-1 (panel columns j < i):
+      // two wavefronts per column j, lanes striding over the rows
+      if (i > 0) {
+        const int j = tid >> 7, h = tid & 127;
+        double s1 = 0.0, s2 = 0.0;
+        if (j < i)
+          for (int r = h; r < n; r += 128) {
+            s1 += Wp[(k + 1 + r) * kPanel + j] * u[r];
+            s2 += Vp[(k + 1 + r) * kPanel + j] * u[r];
+          }
+        for (int o = 32; o > 0; o >>= 1) {
+          s1 += __shfl_xor(s1, o);
+          s2 += __shfl_xor(s2, o);
+        }
+        if ((tid & 63) == 0 && j < i) {
+          ycor[(j * 2 + (h >> 6)) * 2] = s1;
+          ycor[(j * 2 + (h >> 6)) * 2 + 1] = s2;
+        }
+      }
+      __syncthreads();
+      // p = t (B u - V y1 - W y2)
+      if (tid < n) {
+        double p = pp[tid] + pp[kMaxT + tid] + pp[2 * kMaxT + tid] + pp[3 * kMaxT + tid];
+        const int r = k + 1 + tid;
+        for (int j = 0; j < i; ++j) {
+          const double y1 = ycor[(j * 2) * 2] + ycor[(j * 2 + 1) * 2];
+          const double y2 = ycor[(j * 2) * 2 + 1] + ycor[(j * 2 + 1) * 2 + 1];
+          p -= Vp[r * kPanel + j] * y1 + Wp[r * kPanel + j] * y2;
+        }
+        wv[tid] = t * p;
+      }
+      // w = p - (t/2 u^T p) u
+      const double up_ = block_sum(tid < n ? u[tid] * wv[tid] : 0.0, red);
+      const double K = 0.5 * t * up_;
+      if (tid < n) {
+        const double w = wv[tid] - K * u[tid];
+        const int r = k + 1 + tid;
+        Vp[r * kPanel + i] = u[tid];
+        Wp[r * kPanel + i] = w;
+        A[(size_t)r * T + k] = u[tid];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (tid < n) w[tid] = t * (pp[tid] + pp[kMaxT + tid] + pp[2 * kMaxT + tid] + pp[3 * kMaxT + tid]);
-    __syncthreads();
-    // w = p - (t/2 u^T p) u
-    const double up_ = block_sum(tid < n ? v[tid] * w[tid] : 0.0, red);
-    const double K = 0.5 * t * up_;
-    if (tid < n) w[tid] -= K * v[tid];
-    __syncthreads();
-    // B -= u w^T + w u^T, same thread layout
-    for (int c = col; c < n; c += 256) {
-      double* bc = A + (size_t)(k + 1) * T + (k + 1) + c;
-      const double vc = v[c], wc = w[c];
-#pragma unroll 4
-      for (int r = r0; r < r1; ++r) bc[(size_t)r * T] -= v[r] * wc + w[r] * vc;
+    // trailing rows / columns s0 .. T-1: B -= V W^T + W V^T (the panel's
+    // columns of W and V for column c held in registers)
+    const int s0 = k0 + npn, m = T - s0;
+    const int r0 = part * ((m + 3) >> 2), r1 = min(m, r0 + ((m + 3) >> 2));
+    for (int c = s0 + col; c < T; c += 256) {
+      double wc[kPanel], vc[kPanel];
+#pragma unroll
+      for (int j = 0; j < kPanel; ++j) {
+        wc[j] = Wp[c * kPanel + j];
+        vc[j] = Vp[c * kPanel + j];
+      }
+      for (int r = s0 + r0; r < s0 + r1; ++r) {
+        double* ar = A + (size_t)r * T + c;
+        double acc = *ar;
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) acc -= Vp[r * kPanel + j] * wc[j] + Wp[r * kPanel + j] * vc[j];
+        *ar = acc;
+      }
     }
-    if (tid == 0) {
-      d[k] = A[(size_t)k * T + k];
-      e[k] = alpha;
-      tau[k] = t;
-    }
-    if (tid < n) A[(size_t)(k + 1 + tid) * T + k] = v[tid];
-    __syncthreads();
+    k0 += npn;
   }
+  __syncthreads();
   if (tid == 0) {
     if (T >= 2) {
       d[T - 2] = A[(size_t)(T - 2) * T + T - 2];
@@ -326,6 +400,8 @@ __global__ __launch_bounds__(1024) void tri_reduce(const double* __restrict__ G,
     if (T >= 1) tau[T - 1] = 0.0;
   }
 }
+
+size_t tri_reduce_lds(int T) { return 2 * sizeof(double) * (size_t)T * kPanel; }
 
 // Number of eigenvalues of tridiag(e, d, e) below x (Sturm sequence of the
 // LDL^T factorisation of T - x I; zero pivots replaced by -pivmin).
@@ -639,6 +715,7 @@ __global__ __launch_bounds__(256) void power_1pass(const float* __restrict__ x, 
 #pragma unroll
   for (int j = 0; j < NBMAX; ++j) a[j] = 0.0;
   double ss = 0.0;
+#pragma unroll 8
   for (int t = 0; t < T; ++t) {
     const double sv = (double)x[(long long)t * N + n];
     ss = fma(sv, sv, ss);
@@ -782,7 +859,13 @@ hipError_t launch_clutter_filter(const float* x, int T, long long N, int k_lo, i
                        csz, nbk, G);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(tri_reduce, dim3(1), dim3(1024), 0, st, G, T, A, d, e_, tau);
+  {
+    const size_t lds = tri_reduce_lds(T);
+    if ((e = hipFuncSetAttribute((const void*)tri_reduce, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(tri_reduce, dim3(1), dim3(1024), lds, st, G, T, A, d, e_, tau);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(tri_bisect, dim3(T), dim3(64), 0, st, d, e_, T, lam);
   if ((e = hipGetLastError()) != hipSuccess) return e;

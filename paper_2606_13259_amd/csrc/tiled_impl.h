@@ -134,8 +134,11 @@ __device__ inline void stage_load(Stage<BT, QN, MC>& st, const T* __restrict__ w
   for (int k = 0; k < WPW; ++k) {
     const int wi = wave + 4 * k;
     const int q = wi / MC, mc = wi % MC;
+    // 16- and 8-bit codes stay packed (the first BT sizeof(T) / 4 slots)
+    // until the LDS store converts them
+    T u[BT];
 #pragma unroll
-    for (int b = 0; b < BT; ++b) st.v[k][b] = 0.f;
+    for (int b = 0; b < BT; ++b) u[b] = T(0);
     if (wi < QN * MC && q < qn && mc < mcn) {
       // window (q, mc) is wavefront-uniform: scalar base, 32-bit lane offset
       const int e = c0 + mc;
@@ -151,20 +154,48 @@ __device__ inline void stage_load(Stage<BT, QN, MC>& st, const T* __restrict__ w
         // load when they are all present and aligned
         if (BT > 1 && b0 + BT <= B && (reinterpret_cast<uintptr_t>(src) & (BT * sizeof(T) - 1)) == 0) {
           typedef T vecT __attribute__((ext_vector_type(BT)));
-          const vecT u = *reinterpret_cast<const vecT*>(src);
+          const vecT uv = *reinterpret_cast<const vecT*>(src);
 #pragma unroll
-          for (int b = 0; b < BT; ++b) st.v[k][b] = to_f32<T>(u[b]);
+          for (int b = 0; b < BT; ++b) u[b] = uv[b];
         } else {
 #pragma unroll
           for (int b = 0; b < BT; ++b)
-            if (b0 + b < B) st.v[k][b] = to_f32<T>(src[b]);
+            if (b0 + b < B) u[b] = src[b];
         }
       }
+    }
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int b = 0; b < BT; ++b) st.v[k][b] = to_f32<T>(u[b]);
+    } else {
+      constexpr int NW = (BT * (int)sizeof(T) + 3) / 4;
+      uint32_t w[NW];
+#pragma unroll
+      for (int i = 0; i < NW; ++i) w[i] = 0u;
+      __builtin_memcpy(w, u, sizeof(u));
+#pragma unroll
+      for (int i = 0; i < NW; ++i) st.v[k][i] = __uint_as_float(w[i]);
     }
   }
 }
 
-template <int BT, int QN, int MC>
+// Item b of staged window slot k as FP32 (see stage_load).
+template <class T, int BT, int QN, int MC>
+__device__ inline float staged_item(const Stage<BT, QN, MC>& st, int k, int b) {
+  if constexpr (sizeof(T) == 4) {
+    return st.v[k][b];
+  } else {
+    constexpr int NW = (BT * (int)sizeof(T) + 3) / 4;
+    uint32_t w[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = __float_as_uint(st.v[k][i]);
+    T u[BT];
+    __builtin_memcpy(u, w, sizeof(u));
+    return to_f32<T>(u[b]);
+  }
+}
+
+template <class T, int BT, int QN, int MC>
 __device__ inline void stage_store(const Stage<BT, QN, MC>& st, float* win, int mcn, int W,
                                    int wave, int lane) {
   constexpr int WPW = Stage<BT, QN, MC>::WPW;
@@ -176,7 +207,7 @@ __device__ inline void stage_store(const Stage<BT, QN, MC>& st, float* win, int 
     if (wi < QN * MC && mc < mcn && lane < W) {
       float* dst = win + ((mc * WS + lane) * QP + q) * BT;
 #pragma unroll
-      for (int b = 0; b < BT; ++b) dst[b] = st.v[k][b];
+      for (int b = 0; b < BT; ++b) dst[b] = staged_item<T, BT, QN, MC>(st, k, b);
     }
   }
 }
@@ -518,9 +549,9 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           if (vec)
             stage_store4<T, QN, MC>(st, wsm, mcn, W, wave, lane);
           else
-            stage_store<BT, QN, MC>(st, wsm, mcn, W, wave, lane);
+            stage_store<T, BT, QN, MC>(st, wsm, mcn, W, wave, lane);
         } else {
-          stage_store<BT, QN, MC>(st, wsm, mcn, W, wave, lane);
+          stage_store<T, BT, QN, MC>(st, wsm, mcn, W, wave, lane);
         }
         __syncthreads();
         if (c0 + MC < nact) {
@@ -681,9 +712,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BT >= 4 ? 3 
 
 // Complex baseband (IQ) variant: batch items (2b, 2b+1) are the I and Q
 // records of one complex item; every term is remodulated by exp(i 2 pi fc tau)
-// (the same tile schedule and windows as tiled_forward).
+// (the same tile schedule and windows as tiled_forward).  Three wavefronts
+// per SIMD: at four it spilled 192 bytes per lane (cfg2, one complex frame:
+// 8.53 -> 8.09 ms); the two-item real and the cubic kernels keep four, where
+// their smaller spills cost less than the lost wavefront.
 template <class T, int BT, int QN, bool WTX>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void tiled_forward_iq(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void tiled_forward_iq(
     Geom g, TileShape ts, Window win, const T* __restrict__ ws, int B, float* __restrict__ x,
     int ntx, int nty, int ntiles, int nbg) {
   extern __shared__ __align__(16) unsigned char smem[];
