@@ -249,8 +249,10 @@ __device__ inline double block_sum(double v, double* red) {
 // over its gap, also for the weak components of a wide dynamic range.
 
 // 1. A: working copy of G (full, row-major, mirrored from the upper triangle
-// that the Gram kernel forms); on return column k below the diagonal holds
-// the Householder vector u_k (entries k+1 .. T-1).
+// that the Gram kernel forms); on return row k right of the diagonal holds
+// the Householder vector u_k (entries k+1 .. T-1).  Column k of the symmetric
+// working matrix is read as row k, and u_k written there, so both are
+// contiguous.
 //
 // Blocked by panels of kPanel columns: within a panel the trailing matrix is
 // not touched; column k and the product B u_k are corrected on the fly for
@@ -284,11 +286,13 @@ __global__ __launch_bounds__(1024) void tri_reduce(const double* __restrict__ G,
     for (int i = 0; i < npn; ++i) {
       const int k = k0 + i;
       const int n = T - k - 1;  // the trailing block is rows / columns k+1 .. T-1
-      // column k, rows k .. T-1, with the panel's earlier reflectors applied
+      // column k, rows k .. T-1 (read as row k: the panel's start matrix is
+      // symmetric and row k is not written before), with the panel's earlier
+      // reflectors applied
       double a = 0.0;
       if (tid <= n) {
         const int r = k + tid;
-        a = A[(size_t)r * T + k];
+        a = A[(size_t)k * T + r];
         for (int j = 0; j < i; ++j)
           a -= Vp[r * kPanel + j] * Wp[k * kPanel + j] + Wp[r * kPanel + j] * Vp[k * kPanel + j];
         if (tid >= 1) u[tid - 1] = a;
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(1024) void tri_reduce(const double* __restrict__ G,
         const int r = k + 1 + tid;
         Vp[r * kPanel + i] = u[tid];
         Wp[r * kPanel + i] = w;
-        A[(size_t)r * T + k] = u[tid];
+        A[(size_t)k * T + r] = u[tid];
       }
       __syncthreads();
     }
@@ -478,8 +482,9 @@ __device__ inline bool in_projection_basis(const double* lam, int T, int i, int 
 }
 
 // 3. Inverse iteration for the eigenvectors of the projection basis (the
-// others are never used), one workgroup of one wavefront per eigenvector j
-// with lane 0 doing the serial work in LDS: Gaussian elimination with
+// others are never used), one workgroup of one wavefront per eigenvector j:
+// the wavefront copies the tridiagonal matrix to LDS, then lane 0 does the
+// serial work there: Gaussian elimination with
 // partial pivoting of tridiag(e, d, e) - lam_j I (U with two
 // superdiagonals, multipliers and row-swap flags), then three solves from a
 // fixed pseudo-random start, each normalised.  Y[t][j] = component t.
@@ -487,20 +492,27 @@ __global__ __launch_bounds__(64) void tri_inverse(const double* __restrict__ d,
                                                   const double* __restrict__ e,
                                                   const double* __restrict__ lam, int T, int k_lo,
                                                   int k_hi, int keep, double* __restrict__ Y) {
-  __shared__ double U0[kMaxT], U1[kMaxT], U2[kMaxT], L[kMaxT], y[kMaxT];
+  __shared__ double U0[kMaxT], U1[kMaxT], U2[kMaxT], L[kMaxT], y[kMaxT], sd[kMaxT], se[kMaxT];
   __shared__ unsigned char P[kMaxT];
   const int j = blockIdx.x;
-  if (threadIdx.x != 0 || !in_projection_basis(lam, T, j, k_lo, k_hi, keep)) return;
+  if (!in_projection_basis(lam, T, j, k_lo, k_hi, keep)) return;  // uniform
+  // the tridiagonal matrix in LDS (the wavefront), then lane 0 alone
   double anorm = 0.0;
-  for (int t = 0; t < T; ++t)
+  for (int t = threadIdx.x; t < T; t += blockDim.x) {
+    sd[t] = d[t];
+    se[t] = e[t];
     anorm = fmax(anorm, fabs(d[t]) + (t > 0 ? fabs(e[t - 1]) : 0.0) + (t + 1 < T ? fabs(e[t]) : 0.0));
+  }
+  for (int o = 32; o > 0; o >>= 1) anorm = fmax(anorm, __shfl_xor(anorm, o));
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   const double tiny = fmax(1e-280, 2.2e-16 * anorm);
   const double lj = lam[j];
   // the current row has entries (a, b) at (x_t, x_{t+1}); the next original
   // row is (e_t, d_{t+1} - lam, e_{t+1}) at (x_t, x_{t+1}, x_{t+2})
-  double a = d[0] - lj, b = T > 1 ? e[0] : 0.0;
+  double a = sd[0] - lj, b = T > 1 ? se[0] : 0.0;
   for (int t = 0; t + 1 < T; ++t) {
-    const double sub = e[t], na = d[t + 1] - lj, nb = t + 2 < T ? e[t + 1] : 0.0;
+    const double sub = se[t], na = sd[t + 1] - lj, nb = t + 2 < T ? se[t + 1] : 0.0;
     if (fabs(sub) > fabs(a)) {  // swap: the next row is the pivot row
       const double m = a / sub;
       U0[t] = sub;
@@ -570,17 +582,25 @@ __global__ __launch_bounds__(64) void tri_inverse(const double* __restrict__ d,
 // eigenvectors are never used, so they are left as they are; one workgroup.
 __global__ __launch_bounds__(1024) void tri_orth(const double* __restrict__ lam, int T, int k_lo,
                                                  int k_hi, int keep, double* __restrict__ Y) {
-  __shared__ double dots[kMaxT], red[16];
+  __shared__ double dots[kMaxT], ls[kMaxT], red[16];
   __shared__ int in_basis[kMaxT];
   const int tid = threadIdx.x;
-  for (int i = tid; i < T; i += blockDim.x) in_basis[i] = in_projection_basis(lam, T, i, k_lo, k_hi, keep);
-  __syncthreads();
   double lmax = 0.0;
-  for (int j = 0; j < T; ++j) lmax = fmax(lmax, fabs(lam[j]));
+  for (int i = tid; i < T; i += blockDim.x) {
+    in_basis[i] = in_projection_basis(lam, T, i, k_lo, k_hi, keep);
+    ls[i] = lam[i];
+    lmax = fmax(lmax, fabs(lam[i]));
+  }
+  for (int o = 32; o > 0; o >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, o));
+  if ((tid & 63) == 0) red[tid >> 6] = lmax;
+  __syncthreads();
+  lmax = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) lmax = fmax(lmax, red[w]);
+  __syncthreads();  // red is reused by block_sum below
   const double tol = 1e-9 * lmax;
   int cs = 0;  // first vector of the current cluster
   for (int j = 1; j < T; ++j) {
-    if (lam[j] - lam[j - 1] > tol) {
+    if (ls[j] - ls[j - 1] > tol) {
       cs = j;
       continue;
     }
@@ -612,25 +632,30 @@ __global__ __launch_bounds__(1024) void tri_orth(const double* __restrict__ lam,
 }
 
 // 4. V = Q Y for the basis eigenvectors, one workgroup per eigenvector j:
-// the Householder reflectors H_{T-3} .. H_0 applied in turn.
+// the Householder reflectors H_{T-3} .. H_0 applied in turn (u_k read from
+// row k, tau from LDS).
 __global__ __launch_bounds__(256) void tri_back(const double* __restrict__ A,
                                                 const double* __restrict__ tau,
                                                 const double* __restrict__ Y,
                                                 const double* __restrict__ lam, int T, int k_lo,
                                                 int k_hi, int keep, double* __restrict__ V) {
-  __shared__ double y[kMaxT], red[16];
+  __shared__ double y[kMaxT], ts[kMaxT], red[16];
   const int j = blockIdx.x, tid = threadIdx.x;
   if (!in_projection_basis(lam, T, j, k_lo, k_hi, keep)) return;  // uniform
-  for (int t = tid; t < T; t += blockDim.x) y[t] = Y[(size_t)t * T + j];
+  for (int t = tid; t < T; t += blockDim.x) {
+    y[t] = Y[(size_t)t * T + j];
+    ts[t] = tau[t];
+  }
   __syncthreads();
   for (int k = T - 3; k >= 0; --k) {
-    const double tk = tau[k];
+    const double tk = ts[k];
     if (tk == 0.0) continue;  // uniform
     const int n = T - k - 1;
+    const double* uk = A + (size_t)k * T + (k + 1);
     double part = 0.0;
-    for (int i = tid; i < n; i += blockDim.x) part += A[(size_t)(k + 1 + i) * T + k] * y[k + 1 + i];
+    for (int i = tid; i < n; i += blockDim.x) part += uk[i] * y[k + 1 + i];
     const double s = tk * block_sum(part, red);
-    for (int i = tid; i < n; i += blockDim.x) y[k + 1 + i] -= s * A[(size_t)(k + 1 + i) * T + k];
+    for (int i = tid; i < n; i += blockDim.x) y[k + 1 + i] -= s * uk[i];
     __syncthreads();
   }
   for (int t = tid; t < T; t += blockDim.x) V[(size_t)t * T + j] = y[t];
