@@ -37,7 +37,7 @@ namespace {
 constexpr int QG = 16;
 constexpr int NT = 256;
 constexpr int MCA = 4;      // elements per adjoint chunk
-constexpr int ACOPIES = 2;  // private copies of the LDS windows (power of two)
+constexpr int ACOPIES = 4;  // private copies of the LDS windows (power of two; cfg5: 2 copies 2.71 ms, 4 2.04 ms, 8 3.40 ms)
 
 // Floats per window copy (a one-float pad puts the copies on different banks).
 __host__ __device__ inline int copy_stride(int P) { return QG * MCA * P + 1; }
@@ -185,6 +185,12 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
 
 // ----------------------------------------------------------------------------
 
+// One wavefront per 4 x 4 x 4 voxel box (a voxel per lane).  Elements outer,
+// transmits inner, as in the forward kernels: the element's receive geometry
+// and weight are formed once per (voxel, element) and reused by the transmits
+// of a group of QG; elements whose receive cone misses the box's bounding
+// sphere are skipped by the whole wavefront (the weight would be zero on
+// every lane).
 template <int BT>
 __global__ __launch_bounds__(256) void grad_c_gather(Geom g, const float* __restrict__ y,
                                                      const float* __restrict__ gx, int B,
@@ -211,18 +217,39 @@ __global__ __launch_bounds__(256) void grad_c_gather(Geom g, const float* __rest
     const bool inside = in_grid(g, ix, iy, iz);
     const int n = grid_index(g, ix, iy, iz);
     const size_t MK = (size_t)g.M * g.K, QMK = (size_t)g.Q * MK;
+    const bool hann = g.apod == DAS_APOD_HANN_FNUM;
+    const float R = 1.5f * sqrtf((float)(g.s[0] * g.s[0] + g.s[1] * g.s[1] + g.s[2] * g.s[2]));
+    const float tan_half = hann ? 0.5f * sqrtf(4.f / g.fourF2) : 0.f;
     float gxv[BT];
 #pragma unroll
     for (int b = 0; b < BT; ++b) gxv[b] = (inside && b0 + b < B) ? gx[(size_t)(b0 + b) * N + n] : 0.f;
-    for (int q = 0; q < g.Q; ++q) {
-      const TxRef tr = make_tx_ref(g, q, px, py, pz);
-      const float bq = fmaf(delta_tx(tr, dx, dy, dz, dp2), fscf, tr.g);
-      const float wt = (g.w_tx && inside) ? g.w_tx[(size_t)q * N + n] : 1.f;
+    for (int q0 = 0; q0 < g.Q; q0 += QG) {
+      const int qn = min(QG, g.Q - q0);
+      float bq[QG], wq[QG];
+      int ktx[QG];
+#pragma unroll
+      for (int q = 0; q < QG; ++q) {
+        bq[q] = 0.f;
+        wq[q] = 0.f;
+        ktx[q] = 0;
+        if (q < qn) {
+          const TxRef tr = make_tx_ref(g, q0 + q, px, py, pz);
+          bq[q] = fmaf(delta_tx(tr, dx, dy, dz, dp2), fscf, tr.g);
+          wq[q] = (g.w_tx && inside) ? g.w_tx[(size_t)(q0 + q) * N + n] : 1.f;
+          ktx[q] = tr.ktx;
+        }
+      }
       for (int m0 = 0; m0 < g.M; m0 += 64) {
         RxRef mine = {};
-        if (m0 + lane < g.M) mine = make_rx_ref(g, m0 + lane, px, py, pz);
-        const int mn = min(64, g.M - m0);
-        for (int mm = 0; mm < mn; ++mm) {
+        bool on = m0 + lane < g.M;
+        if (on) {
+          mine = make_rx_ref(g, m0 + lane, px, py, pz);
+          if (hann) on = cone_hits_sphere(g, m0 + lane, px, py, pz, R, tan_half);
+        }
+        uint64_t mk = __ballot(on);
+        while (mk) {
+          const int mm = __builtin_ctzll(mk);
+          mk &= mk - 1ull;
           const int m = m0 + mm;
           const float ex = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.ex), mm));
           const float ey = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.ey), mm));
@@ -230,23 +257,29 @@ __global__ __launch_bounds__(256) void grad_c_gather(Geom g, const float* __rest
           const float en = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.en), mm));
           const float h = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine.h), mm));
           const int krx = __builtin_amdgcn_readlane(mine.krx, mm);
-          const float w = wt * rx_weight(g, m, ex + dx, ey + dy, ez + dz);
-          if (w == 0.f) continue;
-          const float f = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, h) + bq;
-          const float fl = floorf(f);
-          const int kb = tr.ktx + krx;
-          const int k = (int)fl + kb;
-          // f + t0 fs in samples, formed in FP32 from its integer and local parts
-          const float fabs_ = (float)kb + f + t0fs;
-          const float dfdc = -fabs_ * inv_c;
-          const float* yq = y + (size_t)q * MK + (size_t)m * g.K;
+          const float w = rx_weight(g, m, ex + dx, ey + dy, ez + dz);
+          if (__ballot(w != 0.f) == 0ull) continue;
+          const float a = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, h);
+          const float* ym = y + (size_t)q0 * MK + (size_t)m * g.K;
 #pragma unroll
-          for (int b = 0; b < BT; ++b) {
-            if (b0 + b < B) {
-              const float* yb = yq + (size_t)(b0 + b) * QMK;
-              const float s1 = (k >= 0 && k < g.K) ? yb[k] : 0.f;
-              const float s2 = (k + 1 >= 0 && k + 1 < g.K) ? yb[k + 1] : 0.f;
-              total = fmaf(gxv[b] * w * dfdc, s2 - s1, total);
+          for (int q = 0; q < QG; ++q) {
+            if (q >= qn) break;
+            const float f = a + bq[q];
+            const float fl = floorf(f);
+            const int kb = ktx[q] + krx;
+            const int k = (int)fl + kb;
+            // f + t0 fs in samples, formed in FP32 from its integer and local parts
+            const float dfdc = -((float)kb + f + t0fs) * inv_c;
+            const float c = w * wq[q] * dfdc;
+            const float* yq = ym + (size_t)q * MK;
+#pragma unroll
+            for (int b = 0; b < BT; ++b) {
+              if (b0 + b < B) {
+                const float* yb = yq + (size_t)(b0 + b) * QMK;
+                const float s1 = (k >= 0 && k < g.K) ? yb[k] : 0.f;
+                const float s2 = (k + 1 >= 0 && k + 1 < g.K) ? yb[k + 1] : 0.f;
+                total = fmaf(gxv[b] * c, s2 - s1, total);
+              }
             }
           }
         }
