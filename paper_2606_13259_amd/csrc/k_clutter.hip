@@ -726,41 +726,66 @@ __global__ __launch_bounds__(256) void project_power(const float* __restrict__ x
 // the kept energy |a|^2 (keep form), and the removal form keeps
 // |s_n|^2 - |a|^2; both in FP64 with the FP64 basis, so the difference is
 // exact to far below the FP32 output even when the removed clutter is many
-// orders above the rest.  One read of the series.  NBMAX >= nb.
-template <int NBMAX>
+// orders above the rest.  One read of the series; VPT neighbouring voxels per
+// thread (one 16-byte load per frame when VPT = 4 and the rows are aligned),
+// so that more bytes are in flight per thread.  NBMAX >= nb.
+template <int NBMAX, int VPT>
 __global__ __launch_bounds__(256) void power_1pass(const float* __restrict__ x, int T, long long N,
                                                    const double* __restrict__ Bd, int nb, int keep,
                                                    float* __restrict__ pd) {
   extern __shared__ double Bs64[];
   for (int i = threadIdx.x; i < T * nb; i += blockDim.x) Bs64[i] = Bd[i];
   __syncthreads();
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  double a[NBMAX];
+  const long long n0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VPT;
+  if (n0 >= N) return;
+  const bool full = VPT == 4 && n0 + VPT <= N && (N & 3) == 0 &&
+                    (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  double a[VPT][NBMAX], ss[VPT];
 #pragma unroll
-  for (int j = 0; j < NBMAX; ++j) a[j] = 0.0;
-  double ss = 0.0;
-#pragma unroll 8
-  for (int t = 0; t < T; ++t) {
-    const double sv = (double)x[(long long)t * N + n];
-    ss = fma(sv, sv, ss);
+  for (int v = 0; v < VPT; ++v) {
+    ss[v] = 0.0;
 #pragma unroll
-    for (int j = 0; j < NBMAX; ++j)
-      if (j < nb) a[j] = fma(sv, Bs64[t * nb + j], a[j]);
+    for (int j = 0; j < NBMAX; ++j) a[v][j] = 0.0;
   }
-  double aa = 0.0;
+#pragma unroll 4
+  for (int t = 0; t < T; ++t) {
+    const float* row = x + (long long)t * N + n0;
+    float s[VPT];
+    if (full) {
+      const f32x4 q = *reinterpret_cast<const f32x4*>(row);
 #pragma unroll
-  for (int j = 0; j < NBMAX; ++j) aa = fma(a[j], a[j], aa);
-  const double p = keep ? aa : fmax(ss - aa, 0.0);
-  pd[n] = (float)(p / T);
+      for (int v = 0; v < VPT; ++v) s[v] = q[v & 3];
+    } else {
+#pragma unroll
+      for (int v = 0; v < VPT; ++v) s[v] = n0 + v < N ? row[v] : 0.f;
+    }
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) {
+      const double sv = (double)s[v];
+      ss[v] = fma(sv, sv, ss[v]);
+#pragma unroll
+      for (int j = 0; j < NBMAX; ++j)
+        if (j < nb) a[v][j] = fma(sv, Bs64[t * nb + j], a[v][j]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) {
+    if (n0 + v >= N) break;
+    double aa = 0.0;
+#pragma unroll
+    for (int j = 0; j < NBMAX; ++j) aa = fma(a[v][j], a[v][j], aa);
+    const double p = keep ? aa : fmax(ss[v] - aa, 0.0);
+    pd[n0 + v] = (float)(p / T);
+  }
 }
 
-template <int NBMAX>
+template <int NBMAX, int VPT>
 hipError_t launch_power_1pass(const float* x, int T, long long N, const double* Bd, int nb, int keep,
                               float* pd, hipStream_t st) {
   const size_t lds = sizeof(double) * (size_t)T * nb;
-  hipLaunchKernelGGL(power_1pass<NBMAX>, dim3((unsigned)((N + 255) / 256)), dim3(256), lds, st, x, T,
-                     N, Bd, nb, keep, pd);
+  const long long per = 256LL * VPT;
+  hipLaunchKernelGGL((power_1pass<NBMAX, VPT>), dim3((unsigned)((N + per - 1) / per)), dim3(256), lds,
+                     st, x, T, N, Bd, nb, keep, pd);
   return hipGetLastError();
 }
 
@@ -904,9 +929,9 @@ hipError_t launch_clutter_filter(const float* x, int T, long long N, int k_lo, i
                      nb);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!xf && nb > 0 && nb <= 16 && sizeof(double) * (size_t)T * nb <= 48 * 1024) {
-    if (nb <= 4) return launch_power_1pass<4>(x, T, N, Bd, nb, keep, pd, st);
-    if (nb <= 8) return launch_power_1pass<8>(x, T, N, Bd, nb, keep, pd, st);
-    return launch_power_1pass<16>(x, T, N, Bd, nb, keep, pd, st);
+    if (nb <= 4) return launch_power_1pass<4, 4>(x, T, N, Bd, nb, keep, pd, st);
+    if (nb <= 8) return launch_power_1pass<8, 1>(x, T, N, Bd, nb, keep, pd, st);
+    return launch_power_1pass<16, 1>(x, T, N, Bd, nb, keep, pd, st);
   }
   if (nb == 0) {  // keep nothing or remove nothing
     return launch_project<1>(x, T, N, Bm, 0, keep, pd, xf, st);
