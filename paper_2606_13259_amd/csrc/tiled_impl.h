@@ -923,6 +923,11 @@ inline size_t lds_bytes(int Q, int bt, const Window& w) {
 template <class T>
 hipError_t launch(const Geom& g, const TileShape& ts, const Window& w, const void* ws, int B,
                   float* x, hipStream_t st) {
+  // eight items per thread when they fill whole groups: a group then reads
+  // 32 of the 64 bytes of an FP32 sample row of 16 items (four items read
+  // 16, and the rest of the fetched row is waste unless another group's
+  // reads hit it in L2), and the delay work is shared by twice the items
+  if (B % 8 == 0) return launch_bt<T, 8>(g, ts, w, ws, B, x, st);
   const int bt = tiled_batch_per_thread(sizeof(T) == 4 ? DAS_STORE_F32 : DAS_STORE_F16, B);
   if (bt == 4) return launch_bt<T, 4>(g, ts, w, ws, B, x, st);
   if (bt == 2) return launch_bt<T, 2>(g, ts, w, ws, B, x, st);
