@@ -52,6 +52,10 @@ constexpr int WS = 64;     // samples per window slot; windows hold W <= WS
 // are then one ds_read2 with offsets q and q + QN + 1 from a per-lane address,
 // and staging writes of consecutive samples do not collide in one bank.
 template <int QN> struct Row { static constexpr int QP = QN + 1; };
+// Floats between consecutive samples of a window: QP entries of BT items,
+// plus 4 for eight items (136 floats would put samples 8 rows apart on the
+// same LDS banks).
+__host__ __device__ constexpr int row_stride(int QN, int BT) { return (QN + 1) * BT + (BT == 8 ? 4 : 0); }
 
 template <class T> __device__ inline float to_f32(T v);
 template <> __device__ inline float to_f32<float>(float v) { return v; }
@@ -84,7 +88,7 @@ __host__ __device__ inline Layout layout(int QN, int MC, int BT, int W) {
   Layout L;
   L.win = 0;
   (void)W;
-  int o = ((MC * WS * (QN + 1) * BT * 4) + 15) & ~15;
+  int o = ((MC * WS * row_stride(QN, BT) * 4) + 15) & ~15;
   L.ex = o; o += EMAX * 4;
   L.ey = o; o += EMAX * 4;
   L.ez = o; o += EMAX * 4;
@@ -199,13 +203,12 @@ template <class T, int BT, int QN, int MC>
 __device__ inline void stage_store(const Stage<BT, QN, MC>& st, float* win, int mcn, int W,
                                    int wave, int lane) {
   constexpr int WPW = Stage<BT, QN, MC>::WPW;
-  constexpr int QP = Row<QN>::QP;
 #pragma unroll
   for (int k = 0; k < WPW; ++k) {
     const int wi = wave + 4 * k;
     const int q = wi / MC, mc = wi % MC;
     if (wi < QN * MC && mc < mcn && lane < W) {
-      float* dst = win + ((mc * WS + lane) * QP + q) * BT;
+      float* dst = win + (mc * WS + lane) * row_stride(QN, BT) + q * BT;
 #pragma unroll
       for (int b = 0; b < BT; ++b) dst[b] = staged_item<T, BT, QN, MC>(st, k, b);
     }
@@ -586,9 +589,9 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
             const double rv = g.fcfs * (double)__builtin_amdgcn_readfirstlane(eK[e]);
             rm = (float)(rv - floor(rv));
           }
-          constexpr int QP = Row<QN>::QP;
           // tap index i = floor(f) + dint is in [1, 2 dint + 1] (window bound)
-          const float* base = wsm + (mc * WS + win.dint) * QP * BT;
+          constexpr int RS = row_stride(QN, BT);
+          const float* base = wsm + (mc * WS + win.dint) * RS;
           // transmits per unit of the tap loop: eight one-item taps, or four
           // with transmit weights, whose sparse lists are short (the loop
           // stops after the unit holding the list's last transmit)
@@ -606,14 +609,14 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
               const float f = a + bq[qa + r];
               if (IQ) fr[IQ ? r : 0] = f;
               al[r] = frac_f32(f);
-              const float* pp = base + (__mul24(floor_i32(f), QP * BT) + (qa + r) * BT);
+              const float* pp = base + (__mul24(floor_i32(f), RS) + (qa + r) * BT);
 #pragma unroll
               for (int b = 0; b < BT; ++b) {
                 s1[r][b] = pp[b];
-                s2[r][b] = pp[QP * BT + b];
+                s2[r][b] = pp[RS + b];
                 if constexpr (CUBIC) {
-                  s0[r][b] = pp[b - QP * BT];
-                  s3[r][b] = pp[2 * QP * BT + b];
+                  s0[r][b] = pp[b - RS];
+                  s3[r][b] = pp[2 * RS + b];
                 }
               }
             }
