@@ -647,7 +647,9 @@ hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b
                                void* ws, hipStream_t st) {
   const int Kc = mfma_chunks(g.K), TW = mfma_tile_width(btot);
   const long long QM = (long long)g.Q * g.M;
-  const dim3 grid((Kc + RC - 1) / RC, (unsigned)std::min<long long>(QM, 65535), (nb + 15) / 16);
+  // at most 1024 channel rows of blocks, each block looping over channels
+  // (cfg2, 256 frames f16: 13.7 -> 12.0-12.9 ms against one block per channel)
+  const dim3 grid((Kc + RC - 1) / RC, (unsigned)std::min<long long>(QM, 1024), (nb + 15) / 16);
   if (storage == DAS_STORE_F16) {
     hipLaunchKernelGGL(reorder_chunks<_Float16>, grid, dim3(256), 0, st, y, g.Q, g.M, g.K, Kc, nb,
                        b0, TW, static_cast<_Float16*>(ws), nullptr);
