@@ -49,6 +49,47 @@ def forward_iq(y_iq, g, fc: float, voxels=None, w_tx=None, c=None) -> np.ndarray
     return x
 
 
+def adjoint_iq(gx, g, fc: float, w_tx=None, c=None) -> np.ndarray:
+    """The transpose of ``forward_iq`` as a real-linear map on (Re, Im) lanes.
+
+    forward_iq is complex-linear in y, so under the real inner product
+    Re(sum a conj(b)) its transpose is the conjugate transpose: each tap of a
+    term receives w conj(exp(i 2 pi fc tau)) times its interpolation weight
+    times the upstream gradient,
+
+        gy[b, q, m, j] = sum_n w exp(-i 2 pi fc tau) ((1-alpha)[j = k] + alpha [j = k+1]) gx[b, n],
+
+    taps outside [0, K) dropped (they read zero in the forward map).  gx:
+    complex [B, N] (or [N]) over the whole grid.  Returns complex128
+    [B, Q, M, K]."""
+    gx = np.asarray(gx, np.complex128)
+    if gx.ndim == 1:
+        gx = gx[None]
+    B = gx.shape[0]
+    Q, M, K = int(np.asarray(g.tx_kind).shape[0]), int(np.asarray(g.elem_pos).shape[0]), int(g.num_samples)
+    c = float(g.c if c is None else c)
+    p = voxel_positions(g)
+    d_tx, wt = _terms(g, p, c, w_tx)
+    gy = np.zeros((B, Q, M, K), np.complex128)
+    for m in range(M):
+        d_rx = np.linalg.norm(p - np.asarray(g.elem_pos, np.float64)[m], axis=1)
+        w_rx = receive_weight(_OneElement(g, m), p)[0]
+        f = fractional_index(d_tx, d_rx[None, :], c, g.fs, g.t0)
+        k = np.floor(f)
+        alpha = f - k
+        k = k.astype(np.int64)
+        tau = (d_tx + d_rx[None, :]) / c
+        wr = wt * w_rx[None, :] * np.exp(-2j * np.pi * fc * tau)             # [Q, n]
+        for b in range(B):
+            for q in range(Q):
+                for tap, cf in ((k[q], 1.0 - alpha[q]), (k[q] + 1, alpha[q])):
+                    ok = (tap >= 0) & (tap < K)
+                    v = wr[q] * cf * gx[b]
+                    gy[b, q, m] += (np.bincount(tap[ok], weights=v[ok].real, minlength=K)
+                                    + 1j * np.bincount(tap[ok], weights=v[ok].imag, minlength=K))
+    return gy
+
+
 def demodulate(y_analytic, fs: float, t0: float, fc: float) -> np.ndarray:
     """Analytic RF records [..., K] -> IQ baseband records (sample k at t0 + k/fs)."""
     K = np.asarray(y_analytic).shape[-1]

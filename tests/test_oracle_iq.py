@@ -62,3 +62,38 @@ def test_baseband_beamformer_matches_the_analytic_rf_one():
     i0 = 10
     assert abs(x_iq[i0] - x_rf[i0]) <= 1e-2 * abs(x_rf[i0])
     assert np.argmax(np.abs(x_iq)) == np.argmax(np.abs(x_rf)) == i0
+
+
+def test_adjoint_iq_dot_product():
+    """adjoint_iq is the transpose of forward_iq under Re(sum a conj(b))."""
+    from oracle.iq import adjoint_iq
+    g = synth.cfg2(dims=(6, 5, 4), n_side=4).replace(num_samples=900)
+    rng = np.random.default_rng(7)
+    y = rng.normal(size=(2, g.Q, g.M, g.K)) + 1j * rng.normal(size=(2, g.Q, g.M, g.K))
+    gx = rng.normal(size=(2, g.N)) + 1j * rng.normal(size=(2, g.N))
+    lhs = np.sum(forward_iq(y, g, fc=7.5e6) * np.conj(gx)).real
+    rhs = np.sum(y * np.conj(adjoint_iq(gx, g, fc=7.5e6))).real
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_adjoint_iq_zero_carrier_is_two_real_adjoints():
+    from oracle.iq import adjoint_iq
+    g = synth.cfg2(dims=(6, 5, 4), n_side=4).replace(num_samples=900)
+    rng = np.random.default_rng(8)
+    gi, gq = rng.normal(size=(2, g.N)), rng.normal(size=(2, g.N))
+    gy = adjoint_iq(gi + 1j * gq, g, fc=0.0)
+    ref = oracle.adjoint(gi, g) + 1j * oracle.adjoint(gq, g)
+    assert np.allclose(gy, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("fc", [7.5e6, 5.0e6])
+def test_adjoint_iq_hand_phase_on_a_3_4_5_triangle(fc):
+    """The 3-4-5 voxel of the forward pin: a unit upstream gradient lands on
+    the two taps of the 9 mm path with weights summing to
+    exp(-i 2 pi fc 9 mm / c)."""
+    from oracle.iq import adjoint_iq
+    c = 1540.0
+    g = _one_voxel_geometry((0.0, 0.0, 0.0), (3e-3, 0.0, 4e-3), c=c)
+    gy = adjoint_iq(np.ones((1, 1), np.complex128), g, fc=fc)
+    assert np.count_nonzero(gy) <= 2
+    assert gy.sum() == pytest.approx(np.exp(-2j * np.pi * fc * 9e-3 / c), abs=1e-12)
