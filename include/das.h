@@ -143,8 +143,9 @@ das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
  * windowed algorithm with f32 storage, or in the MFMA algorithm with f16 or
  * FP8 storage (Alg. 3's complex W: the cosine and sine parts of the weights
  * contracted with the same sample fragments; COLUMN or SLAB launch), with an
- * even batch (DAS_ERR_UNSUPPORTED / DAS_ERR_INVALID_ARG otherwise);
- * das_adjoint, das_grad_sound_speed and das_forward_batched refuse IQ plans.
+ * even batch (DAS_ERR_UNSUPPORTED / DAS_ERR_INVALID_ARG otherwise).
+ * das_adjoint of an IQ plan is the transpose of that map (even batch);
+ * das_grad_sound_speed and das_forward_batched refuse IQ plans.
  * enable = 0 restores real data. */
 das_status das_plan_set_iq(das_plan p, int32_t enable, double fc);
 /* Launch form of the MFMA algorithm (Sec. 3.4, Alg. 3); Sec. 3.2 says tile
@@ -230,6 +231,10 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
  * gy[b][q][m][j] = sum_n w_qmn ((1-a)[j = k] + a [j = k+1]) gx[b][n].
  * gx: device [batch][N] f32; gy: device [batch][Q][M][K] f32, overwritten
  * (taps outside [0, K) are dropped, as they read zero in the forward map).
+ * IQ plans (das_plan_set_iq; even batch): the transpose of the complex
+ * baseband map, item pairs (2b, 2b+1) = (I, Q) on both sides:
+ * gy[2b] + i gy[2b+1] at tap j = sum_n w_qmn ((1-a)[j = k] + a [j = k+1])
+ * exp(-i 2 pi fc tau) (gx[2b][n] + i gx[2b+1][n]).
  * Summation order across voxel tiles is not fixed (FP32 rounding level). */
 das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, void* stream);
 

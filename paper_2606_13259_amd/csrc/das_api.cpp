@@ -601,11 +601,11 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
 
 das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, void* stream) {
   if (das_status s = check_plan(p)) return s;
-  if (p->iq) return fail(DAS_ERR_UNSUPPORTED, "the adjoint of the complex baseband form is not built");
   if (p->interp != DAS_INTERP_LINEAR)
     return fail(DAS_ERR_UNSUPPORTED, "the adjoint is built for linear interpolation only");
   if (!gx || !gy) return fail(DAS_ERR_INVALID_ARG, "gx or gy is NULL");
   if (das_status s = check_batch(p, batch)) return s;
+  if (p->iq && batch % 2) return fail(DAS_ERR_INVALID_ARG, "complex baseband needs an even batch");
   DeviceGuard dg(p->device);
   const Geom g = make_geom(p);
   const TileShape ts = tile_shape(p->tile);

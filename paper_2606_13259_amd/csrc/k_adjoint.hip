@@ -58,6 +58,14 @@ struct AInfo {
   int krx, m, pad;
 };
 
+// IQ: the complex baseband form's transpose (items 2c, 2c+1 are the I and Q
+// lanes of complex item c = blockIdx.y): each tap receives
+// w conj(exp(i 2 pi fc tau)) times the complex upstream gradient, i.e.
+// w (cos gI + sin gQ) into the I record and w (cos gQ - sin gI) into the Q
+// record, with the phase of the forward (transmit and element parts in FP64,
+// the tile-relative part in FP32, hardware sine and cosine on revolutions);
+// two sets of windows.
+template <bool IQ>
 __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Window win,
                                                       const float* __restrict__ gx, int B,
                                                       float* __restrict__ gy, int ntx, int nty,
@@ -66,7 +74,8 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
   const int P = win.pairs + 1;  // window samples
   const int cs = copy_stride(P);
   int* accw = reinterpret_cast<int*>(smem);                           // [ACOPIES][QG][MCA][P] (+pad)
-  AInfo* minfo = reinterpret_cast<AInfo*>(accw + ACOPIES * cs);        // [MCA]
+  constexpr int NS = IQ ? 2 : 1;                                       // window sets (I, Q)
+  AInfo* minfo = reinterpret_cast<AInfo*>(accw + NS * ACOPIES * cs);   // [MCA]
   int* ktxs = reinterpret_cast<int*>(minfo + MCA);                      // [QG]
   int* wcount = ktxs + QG;                                              // [4] (also the scale reduction)
   uint16_t* act = reinterpret_cast<uint16_t*>(wcount + 4);              // [M]
@@ -74,7 +83,7 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (tile >= ntiles) return;
-  const int b = blockIdx.y;
+  const int b = IQ ? 2 * blockIdx.y : blockIdx.y;  // the I item for IQ
   const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = tile / (ntx * nty);
   const int lx = t & (ts.tx - 1), ly = (t >> ts.lx) & (ts.ty - 1), lz = t >> ts.lxy;
   const int ix = tix * ts.tx + lx, iy = tiy * ts.ty + ly, iz = tiz * ts.tz + lz;
@@ -93,34 +102,47 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
   const bool inside = in_grid(g, ix, iy, iz);
   const int n = grid_index(g, ix, iy, iz);
   const float gv = inside ? gx[(size_t)b * N + n] : 0.f;
+  const float gvq = IQ && inside ? gx[(size_t)(b + 1) * N + n] : 0.f;
 
   const int nact = cull_elements(g, px, py, pz, hx, hy, hz, wcount, act);
   // a tile whose upstream gradient is zero everywhere scatters nothing
-  if (__syncthreads_or(gv != 0.f) == 0) return;
+  if (__syncthreads_or(gv != 0.f || gvq != 0.f) == 0) return;
   // windows start at zero; every flush leaves the entries it reads at zero
-  for (int i = t; i < ACOPIES * cs; i += NT) accw[i] = 0;
+  for (int i = t; i < NS * ACOPIES * cs; i += NT) accw[i] = 0;
   int* const mycopy = accw + (lx & (ACOPIES - 1)) * cs;
+  int* const mycopyq = mycopy + ACOPIES * cs;  // IQ: the Q windows
+  const float fcfs_f = (float)g.fcfs;
 
   for (int q0 = 0; q0 < g.Q; q0 += QG) {
     const int qn = min(QG, g.Q - q0);
     __syncthreads();
     if (t < qn) ktxs[t] = make_tx_ref(g, q0 + t, px, py, pz).ktx;
     float bq[QG], wq[QG];
+    float wqq[IQ ? QG : 1], rq[IQ ? QG : 1];  // IQ: Q gradient and transmit phase
 #pragma unroll
     for (int q = 0; q < QG; ++q) {
       bq[q] = 0.f;
       wq[q] = 0.f;
+      if constexpr (IQ) wqq[q] = rq[q] = 0.f;
       if (q < qn) {
         const TxRef r = make_tx_ref(g, q0 + q, px, py, pz);
         bq[q] = fmaf(delta_tx(r, dx, dy, dz, dp2), fscf, r.g);
-        wq[q] = gv * ((g.w_tx && inside) ? g.w_tx[(size_t)(q0 + q) * N + n] : 1.f);
+        const float wt = (g.w_tx && inside) ? g.w_tx[(size_t)(q0 + q) * N + n] : 1.f;
+        wq[q] = gv * wt;
+        if constexpr (IQ) {
+          // the transmit's phase term frac(fc/fs ktx + fc t0), FP64 before rounding
+          const double rv = g.fcfs * (double)r.ktx + g.fct0;
+          rq[q] = (float)(rv - floor(rv));
+          wqq[q] = gvq * wt;
+        }
       }
     }
     // fixed-point scale of this transmit group: max |contribution| over the
-    // tile (receive weights are <= 1), then S = 2^(22 - e) with cmax < 2^e
+    // tile (receive weights are <= 1; a rotated complex gradient is bounded
+    // by |gI| + |gQ|), then S = 2^(22 - e) with cmax < 2^e
     float cm = 0.f;
 #pragma unroll
-    for (int q = 0; q < QG; ++q) cm = fmaxf(cm, fabsf(wq[q]));
+    for (int q = 0; q < QG; ++q) cm = fmaxf(cm, IQ ? fabsf(wq[q]) + fabsf(wqq[IQ ? q : 0]) : fabsf(wq[q]));
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) cm = fmaxf(cm, __shfl_xor(cm, o));
     if (lane == 0) wcount[wave] = __float_as_int(cm);  // non-negative: int order = float order
@@ -141,33 +163,58 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
       for (int mc = 0; mc < mcn; ++mc) {
         const AInfo mi = minfo[mc];
         const float w = rx_weight(g, mi.m, mi.ex + dx, mi.ey + dy, mi.ez + dz);
-        if (__ballot(w != 0.f && gv != 0.f) == 0ull) continue;
+        if (__ballot(w != 0.f && (gv != 0.f || gvq != 0.f)) == 0ull) continue;
         const float a = fmaf(delta_dist(mi.ex, mi.ey, mi.ez, mi.en, dx, dy, dz, dp2), fscf, mi.h);
         int* base = mycopy + mc * P + win.dint;
+        int* baseq = mycopyq + mc * P + win.dint;
+        float rm = 0.f;  // IQ: the element's phase term frac(fc/fs krx)
+        if constexpr (IQ) {
+          const double rv = g.fcfs * (double)mi.krx;
+          rm = (float)(rv - floor(rv));
+        }
 #pragma unroll
         for (int q = 0; q < QG; ++q) {
           if (q < qn) {
             const float f = a + bq[q];
             const float fl = floorf(f);
             const float al = f - fl;
-            const float c = w * wq[q];
-            if (c != 0.f) {
-              int* p = base + q * MCA * P + (int)fl;
-              const float cs2 = c * S;  // exact: S is a power of two
-              atomicAdd(p, __float2int_rn(cs2 - cs2 * al));
-              atomicAdd(p + 1, __float2int_rn(cs2 * al));
+            const int off = q * MCA * P + (int)fl;
+            if constexpr (IQ) {
+              // conjugate rotation: revolutions fc/fs (ktx + krx + f) + fc t0
+              const float rev = frac_f32(rq[q] + rm + fcfs_f * f);
+              const float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
+              const float ci = w * fmaf(cs, wq[q], sn * wqq[q]);
+              const float cq = w * fmaf(cs, wqq[q], -sn * wq[q]);
+              if (ci != 0.f) {
+                const float cs2 = ci * S;
+                atomicAdd(base + off, __float2int_rn(cs2 - cs2 * al));
+                atomicAdd(base + off + 1, __float2int_rn(cs2 * al));
+              }
+              if (cq != 0.f) {
+                const float cs2 = cq * S;
+                atomicAdd(baseq + off, __float2int_rn(cs2 - cs2 * al));
+                atomicAdd(baseq + off + 1, __float2int_rn(cs2 * al));
+              }
+            } else {
+              const float c = w * wq[q];
+              if (c != 0.f) {
+                const float cs2 = c * S;  // exact: S is a power of two
+                atomicAdd(base + off, __float2int_rn(cs2 - cs2 * al));
+                atomicAdd(base + off + 1, __float2int_rn(cs2 * al));
+              }
             }
           }
         }
       }
       __syncthreads();
-      // flush: wave w flushes windows w, w+4, ...
-      for (int wi = wave; wi < QG * MCA; wi += 4) {
-        const int q = wi / MCA, mc = wi % MCA;
+      // flush: wave w flushes windows w, w+4, ... (IQ: then the Q windows
+      // into item b + 1)
+      for (int wi = wave; wi < NS * QG * MCA; wi += 4) {
+        const int set = wi / (QG * MCA), q = (wi / MCA) % QG, mc = wi % MCA;
         if (q >= qn || mc >= mcn) continue;
         const int j0 = ktxs[q] + minfo[mc].krx - win.dint;
-        float* dst = gy + (((size_t)b * g.Q + q0 + q) * M + minfo[mc].m) * (size_t)K;
-        int* src = accw + (q * MCA + mc) * P;
+        float* dst = gy + (((size_t)(b + set) * g.Q + q0 + q) * M + minfo[mc].m) * (size_t)K;
+        int* src = accw + set * ACOPIES * cs + (q * MCA + mc) * P;
         for (int p = lane; p < P; p += 64) {
           int iv = 0;
 #pragma unroll
@@ -325,7 +372,7 @@ __global__ void debug_delays(Geom g, TileShape ts, int q, int m0, int m1, int n0
 
 size_t adjoint_lds_bytes(const Geom& g, const Window& w) {
   const int P = w.pairs + 1;
-  size_t lds = (size_t)ACOPIES * copy_stride(P) * 4 + MCA * sizeof(AInfo) + QG * 4 + 16 +
+  size_t lds = (size_t)(g.iq ? 2 : 1) * ACOPIES * copy_stride(P) * 4 + MCA * sizeof(AInfo) + QG * 4 + 16 +
                (size_t)g.M * 2;
   return (lds + 15) & ~(size_t)15;
 }
@@ -339,13 +386,18 @@ hipError_t launch_adjoint(const Geom& g, const TileShape& ts, const Window& w, c
   const int ntiles = ntx * nty * ntz;
   const int per_xcd = (ntiles + 7) / 8;
   const size_t lds = adjoint_lds_bytes(g, w);
+  // complex baseband: one workgroup per (I, Q) item pair
+  const void* kern = g.iq ? (const void*)adjoint_scatter<true> : (const void*)adjoint_scatter<false>;
   if (lds > 65536) {
-    e = hipFuncSetAttribute((const void*)adjoint_scatter,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(adjoint_scatter, dim3(per_xcd * 8, B), dim3(NT), lds, st, g, ts, w, gx, B, gy,
-                     ntx, nty, ntiles, per_xcd);
+  if (g.iq)
+    hipLaunchKernelGGL(adjoint_scatter<true>, dim3(per_xcd * 8, B / 2), dim3(NT), lds, st, g, ts, w,
+                       gx, B, gy, ntx, nty, ntiles, per_xcd);
+  else
+    hipLaunchKernelGGL(adjoint_scatter<false>, dim3(per_xcd * 8, B), dim3(NT), lds, st, g, ts, w,
+                       gx, B, gy, ntx, nty, ntiles, per_xcd);
   return hipGetLastError();
 }
 

@@ -323,7 +323,8 @@ class Plan:
 
     def set_iq(self, fc: float, enable: bool = True):
         """Complex baseband mode: batch items are (I, Q) pairs demodulated at
-        fc (Hz); the forward remodulates every term by exp(i 2 pi fc tau)."""
+        fc (Hz); the forward remodulates every term by exp(i 2 pi fc tau) and
+        the adjoint applies the conjugate phase."""
         _check(lib().das_plan_set_iq(self.handle, int(bool(enable)), float(fc)), "das_plan_set_iq")
 
     def set_interp(self, interp: str):

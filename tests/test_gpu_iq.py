@@ -1,15 +1,16 @@
-"""Complex baseband (IQ) beamforming on the MI355X against the FP64 oracle
-(oracle.iq.forward_iq).  The phase rotation is formed from FP64 per-tile
-phase terms plus an FP32 tile-relative part (a few 1e-7 revolutions) and the
-hardware sine and cosine of the revolution count; the bar is the FP32 one
-(rel-L2 and elementwise 1e-5 against the FP64 oracle)."""
+"""Complex baseband (IQ) beamforming and its transpose on the MI355X against
+the FP64 oracle (oracle.iq.forward_iq, oracle.iq.adjoint_iq).  The phase
+rotation is formed from FP64 per-tile phase terms plus an FP32 tile-relative
+part (a few 1e-7 revolutions) and the hardware sine and cosine of the
+revolution count; the bar is the FP32 one (rel-L2 and elementwise 1e-5
+against the FP64 oracle)."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import synth
-from oracle.iq import demodulate, forward_iq
+from oracle.iq import adjoint_iq, demodulate, forward_iq
 from paper_2606_13259_amd import metrics
 from tests.gpu_util import ABS_F32, REL_L2_F32, cfg2_channel_data, check_close, say
 
@@ -95,8 +96,8 @@ def test_iq_refusals(gpu):
         p.forward(synth.random_channel_data(g, 3, seed=1).to(gpu))
     assert e.value.status == das.DAS_ERR_INVALID_ARG
     with pytest.raises(das.DasError) as e:
-        p.adjoint(torch.zeros(2, p.N, device=gpu))
-    assert e.value.status == das.DAS_ERR_UNSUPPORTED
+        p.adjoint(torch.zeros(3, p.N, device=gpu))
+    assert e.value.status == das.DAS_ERR_INVALID_ARG
     p16 = das.Plan(g, max_batch=4, storage="f16", algo="tiled")
     p16.set_iq(7.5e6)
     with pytest.raises(das.DasError) as e:
@@ -105,6 +106,68 @@ def test_iq_refusals(gpu):
     with pytest.raises(das.DasError) as e:
         p.set_iq(-1.0)
     assert e.value.status == das.DAS_ERR_INVALID_ARG
+
+
+# --- the transpose of the complex baseband map (oracle.iq.adjoint_iq) ---
+
+def _run_adjoint(g, gx, fc, gpu, w_tx=None):
+    """gx complex [C, N] -> GPU gy complex [C, Q, M, K] (I/Q interleaved items)."""
+    das = _das()
+    C = gx.shape[0]
+    lanes = np.empty((2 * C, g.N), np.float32)
+    lanes[0::2] = gx.real
+    lanes[1::2] = gx.imag
+    plan = das.Plan(g, max_batch=2 * C, storage="f32", algo="tiled")
+    plan.set_iq(fc)
+    if w_tx is not None:
+        plan.set_tx_weights(torch.from_numpy(w_tx).to(gpu))
+    gy = plan.adjoint(torch.from_numpy(lanes).to(gpu)).cpu().numpy().astype(np.float64)
+    return gy[0::2] + 1j * gy[1::2]
+
+
+@pytest.mark.parametrize("C,fc", [(1, 7.5e6), (2, 3.1e6)])
+def test_iq_adjoint_vs_oracle(gpu, C, fc):
+    g = _geometry()
+    rng = np.random.default_rng(40 + C)
+    gx = rng.normal(size=(C, g.N)) + 1j * rng.normal(size=(C, g.N))
+    gx = gx.astype(np.complex64)  # the values the GPU receives
+    gy = _run_adjoint(g, gx, fc, gpu)
+    gyo = adjoint_iq(gx, g, fc)
+    for c in range(C):
+        check_close(np.concatenate([gy[c].real.ravel(), gy[c].imag.ravel()]),
+                    np.concatenate([gyo[c].real.ravel(), gyo[c].imag.ravel()]),
+                    REL_L2_F32, ABS_F32, f"IQ adjoint fc={fc / 1e6} MHz item {c}")
+
+
+def test_iq_adjoint_tx_weights(gpu):
+    """Spatially selective transmit weights (about half of each transmit's
+    voxels at zero) scaled by random factors."""
+    sub = _geometry()
+    rng = np.random.default_rng(44)
+    w = synth.selective_tx_weights(sub) * rng.uniform(0.2, 1.0, size=(sub.Q, sub.N)).astype(np.float32)
+    assert np.count_nonzero(w) > 0
+    gx = (rng.normal(size=(1, sub.N)) + 1j * rng.normal(size=(1, sub.N))).astype(np.complex64)
+    gy = _run_adjoint(sub, gx, 7.5e6, gpu, w_tx=w)
+    gyo = adjoint_iq(gx, sub, 7.5e6, w_tx=w)
+    check_close(np.concatenate([gy[0].real.ravel(), gy[0].imag.ravel()]),
+                np.concatenate([gyo[0].real.ravel(), gyo[0].imag.ravel()]),
+                REL_L2_F32, ABS_F32, "IQ adjoint with transmit weights")
+
+
+def test_iq_adjoint_dot_product(gpu):
+    """<A y, x> = <y, A^T x> in the real inner product over the I/Q lanes,
+    both sides through the windowed kernels."""
+    das = _das()
+    g = _geometry()
+    rng = np.random.default_rng(45)
+    y = torch.from_numpy(rng.normal(size=(4, g.Q, g.M, g.K)).astype(np.float32)).to(gpu)
+    x = torch.from_numpy(rng.normal(size=(4, g.N)).astype(np.float32)).to(gpu)
+    plan = das.Plan(g, max_batch=4, storage="f32", algo="tiled")
+    plan.set_iq(7.5e6)
+    lhs = float((plan.forward(y).double() * x.double()).sum())
+    rhs = float((y.double() * plan.adjoint(x).double()).sum())
+    say(f"  <Ay,x>={lhs:.9e} <y,A^T x>={rhs:.9e} (IQ)")
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
 # --- complex baseband in the MFMA locality form (Alg. 3 with complex W) ---
