@@ -89,6 +89,50 @@ def adjoint_iq(gx, g, fc: float, w_tx=None, c=None) -> np.ndarray:
                                     + 1j * np.bincount(tap[ok], weights=v[ok].imag, minlength=K))
     return gy
 
+def dforward_dc_iq(y_iq, g, fc: float, voxels=None, w_tx=None, c=None) -> np.ndarray:
+    """d x[b, n] / d c of ``forward_iq``.  Both the fractional index and the
+    phase depend on c through tau = (D_tx + D_rx)/c, dtau/dc = -tau/c:
+
+        dx/dc = sum_q sum_m w exp(i 2 pi fc tau)
+                ((s(k+1) - s(k)) df/dc + i 2 pi fc dtau/dc ((1-alpha) s(k) + alpha s(k+1))),
+
+    with df/dc = fs dtau/dc (the right-hand slope at integer f, as for the
+    real form, reading R8).  Returns complex128 [B, n]."""
+    y = np.asarray(y_iq, np.complex128)
+    if y.ndim == 3:
+        y = y[None]
+    B, Q, M, K = y.shape
+    c = float(g.c if c is None else c)
+    p = voxel_positions(g, voxels)
+    d_tx, wt = _terms(g, p, c, w_tx)
+    out = np.zeros((B, p.shape[0]), np.complex128)
+    for m in range(M):
+        d_rx = np.linalg.norm(p - np.asarray(g.elem_pos, np.float64)[m], axis=1)
+        w_rx = receive_weight(_OneElement(g, m), p)[0]
+        f = fractional_index(d_tx, d_rx[None, :], c, g.fs, g.t0)
+        k = np.floor(f)
+        alpha = f - k
+        k = k.astype(np.int64)
+        tau = (d_tx + d_rx[None, :]) / c
+        dtau = -tau / c
+        rot = np.exp(2j * np.pi * fc * tau)
+        w = wt * w_rx[None, :]
+        trace = y[:, :, m, :]
+        s1 = sample(trace.real, k) + 1j * sample(trace.imag, k)
+        s2 = sample(trace.real, k + 1) + 1j * sample(trace.imag, k + 1)
+        interp = (1.0 - alpha[None]) * s1 + alpha[None] * s2
+        slope = (s2 - s1) * (g.fs * dtau)[None]
+        turn = 2j * np.pi * fc * dtau[None] * interp
+        out += np.sum((w * rot)[None] * (slope + turn), axis=1)
+    return out
+
+
+def grad_sound_speed_iq(y_iq, gx, g, fc: float, w_tx=None, c=None) -> float:
+    """dL/dc for a real loss of the complex image with upstream gradient
+    gx = dL/dRe x + i dL/dIm x: sum_{b, n} Re(conj(gx) dx/dc)."""
+    d = dforward_dc_iq(y_iq, g, fc, None, w_tx, c)
+    return float(np.sum((np.conj(np.asarray(gx, np.complex128).reshape(d.shape)) * d).real))
+
 
 def demodulate(y_analytic, fs: float, t0: float, fc: float) -> np.ndarray:
     """Analytic RF records [..., K] -> IQ baseband records (sample k at t0 + k/fs)."""

@@ -97,3 +97,52 @@ def test_adjoint_iq_hand_phase_on_a_3_4_5_triangle(fc):
     gy = adjoint_iq(np.ones((1, 1), np.complex128), g, fc=fc)
     assert np.count_nonzero(gy) <= 2
     assert gy.sum() == pytest.approx(np.exp(-2j * np.pi * fc * 9e-3 / c), abs=1e-12)
+
+
+def test_dforward_dc_iq_vs_finite_differences():
+    """Central differences of forward_iq in c with a step too small for any
+    tap index to change (checked): the interpolant is linear in f between
+    integers and the phase is smooth in c, so the quotient equals the
+    analytic derivative up to rounding."""
+    from oracle.iq import dforward_dc_iq
+    g = synth.sub_grid(synth.cfg5(), (28, 28, 20), (4, 4, 4))
+    rng = np.random.default_rng(9)
+    y = rng.normal(size=(1, g.Q, g.M, g.K)) + 1j * rng.normal(size=(1, g.Q, g.M, g.K))
+    fc, h = 7.5e6, 2e-6
+    p = oracle.voxel_positions(g)
+    path = oracle.transmit_path(g, p)[:, None, :] + oracle.receive_path(g, p)[None, :, :]
+    k_lo = np.floor(oracle.fractional_index(path, 0.0, g.c - h, g.fs, g.t0))
+    k_hi = np.floor(oracle.fractional_index(path, 0.0, g.c + h, g.fs, g.t0))
+    assert np.array_equal(k_lo, k_hi)
+    d = dforward_dc_iq(y, g, fc)
+    fd = (forward_iq(y, g, fc, c=g.c + h) - forward_iq(y, g, fc, c=g.c - h)) / (2 * h)
+    assert np.linalg.norm(fd - d) / np.linalg.norm(d) < 1e-7
+    # the phase term matters: without it the quotient is far off
+    d_real = oracle.dforward_dc(y.real, g) + 1j * oracle.dforward_dc(y.imag, g)
+    assert np.linalg.norm(fd - d_real) / np.linalg.norm(d) > 0.1
+
+
+def test_dforward_dc_iq_zero_carrier_is_two_real_derivatives():
+    from oracle.iq import dforward_dc_iq
+    g = synth.cfg2(dims=(6, 5, 4), n_side=4).replace(num_samples=900)
+    rng = np.random.default_rng(10)
+    yi, yq = rng.normal(size=(2, g.Q, g.M, g.K)), rng.normal(size=(2, g.Q, g.M, g.K))
+    d = dforward_dc_iq(yi + 1j * yq, g, fc=0.0)
+    ref = oracle.dforward_dc(yi, g) + 1j * oracle.dforward_dc(yq, g)
+    assert np.allclose(d, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("fc", [7.5e6, 5.0e6])
+def test_dforward_dc_iq_hand_value_on_a_3_4_5_triangle(fc):
+    """Constant baseband data on the 3-4-5 voxel: x(c) = exp(i 2 pi fc L / c)
+    with L = 9 mm, so dx/dc = -i 2 pi fc L / c^2 x (the slope term vanishes),
+    and the loss gradient for gx = 1 - 2i is Re(conj(gx) dx/dc)."""
+    from oracle.iq import dforward_dc_iq, grad_sound_speed_iq
+    c, L = 1540.0, 9e-3
+    g = _one_voxel_geometry((0.0, 0.0, 0.0), (3e-3, 0.0, 4e-3), c=c)
+    y = np.ones((1, 1, 1, g.K), np.complex128)
+    x = np.exp(2j * np.pi * fc * L / c)
+    want = -2j * np.pi * fc * L / c ** 2 * x
+    assert dforward_dc_iq(y, g, fc)[0, 0] == pytest.approx(want, rel=1e-12)
+    gx = np.array([[1.0 - 2.0j]])
+    assert grad_sound_speed_iq(y, gx, g, fc) == pytest.approx((np.conj(gx[0, 0]) * want).real, rel=1e-12)
