@@ -442,26 +442,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBMAX == 4 
 
 // y[nb][Q][M][K] f32 -> batch-tiled chunked workspace ws[Bp/TW][Q][M][Kc][TW][8]
 // for items b0 .. b0+nb-1.  A workgroup converts 32 chunks (256 samples) of 16 items of
-// one channel (q, m): rows of 256 samples are read coalesced into LDS, then
-// each thread packs two 8-sample chunks, the 16 items of a chunk being
-// adjacent 16-byte stores.
+// one channel (q, m): rows of 256 samples are read coalesced into LDS (vec:
+// K a multiple of 4 and y 16-byte aligned, each thread loads four samples of
+// four rows with 16-byte loads, all issued before the LDS writes; else one
+// sample of each row), then each thread packs two 8-sample chunks, the 16
+// items of a chunk being adjacent 16-byte stores.
 constexpr int RC = 32;  // chunks per reorder tile
 template <class T>
 __global__ __launch_bounds__(256) void reorder_chunks(const float* __restrict__ y, int Q, int M,
                                                       int K, int Kc, int nb, int b0, int TW,
                                                       T* __restrict__ ws,
-                                                      const float* __restrict__ amax) {
+                                                      const float* __restrict__ amax, int vec) {
   __shared__ float tile[16][RC * CH + 1];
   const long long QM = (long long)Q * M;
   const int t = threadIdx.x;
   const int kc0 = blockIdx.x * RC;
   const int i0 = blockIdx.z * 16;  // first item of this tile (relative to b0)
   for (long long qm = blockIdx.y; qm < QM; qm += gridDim.y) {
-    const int k = CH * (kc0 - 1) + t;
+    if (vec) {
+      // rows r, r + 4, r + 8, r + 12; samples 4 (t % 64) .. +3 of the tile.
+      // With K a multiple of 4 the four samples are all inside [0, K) or all
+      // outside (the tile starts at a multiple of 8).
+      const int r = t >> 6, k4 = (t & 63) * 4;
+      const int k = CH * (kc0 - 1) + k4;
+      f32x4 v[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int b = i0 + r + 4 * p;
+        v[p] = (b < nb && k >= 0 && k < K)
+                   ? *reinterpret_cast<const f32x4*>(y + ((long long)b * QM + qm) * K + k)
+                   : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) tile[r + 4 * p][k4 + c] = v[p][c];
+    } else {
+      const int k = CH * (kc0 - 1) + t;
 #pragma unroll 4
-    for (int i = 0; i < 16; ++i) {
-      const int b = i0 + i;
-      tile[i][t] = (b < nb && k >= 0 && k < K) ? y[((long long)b * QM + qm) * K + k] : 0.f;
+      for (int i = 0; i < 16; ++i) {
+        const int b = i0 + i;
+        tile[i][t] = (b < nb && k >= 0 && k < K) ? y[((long long)b * QM + qm) * K + k] : 0.f;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -650,17 +672,18 @@ hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b
   // at most 1024 channel rows of blocks, each block looping over channels
   // (cfg2, 256 frames f16: 13.7 -> 12.0-12.9 ms against one block per channel)
   const dim3 grid((Kc + RC - 1) / RC, (unsigned)std::min<long long>(QM, 1024), (nb + 15) / 16);
+  const int vec = g.K % 4 == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0;
   if (storage == DAS_STORE_F16) {
     hipLaunchKernelGGL(reorder_chunks<_Float16>, grid, dim3(256), 0, st, y, g.Q, g.M, g.K, Kc, nb,
-                       b0, TW, static_cast<_Float16*>(ws), nullptr);
+                       b0, TW, static_cast<_Float16*>(ws), nullptr, vec);
   } else if (storage == DAS_STORE_FP8_E4M3) {
     hipError_t e = launch_item_absmax(g, y, b0, nb, const_cast<float*>(g.amax), st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reorder_chunks<uint8_t>, grid, dim3(256), 0, st, y, g.Q, g.M, g.K, Kc, nb,
-                       b0, TW, static_cast<uint8_t*>(ws), g.amax);
+                       b0, TW, static_cast<uint8_t*>(ws), g.amax, vec);
   } else {
     hipLaunchKernelGGL(reorder_chunks<uint16_t>, grid, dim3(256), 0, st, y, g.Q, g.M, g.K, Kc, nb,
-                       b0, TW, static_cast<uint16_t*>(ws), nullptr);
+                       b0, TW, static_cast<uint16_t*>(ws), nullptr, vec);
   }
   return hipGetLastError();
 }
