@@ -375,8 +375,8 @@ def main():
     if args.adjoint:
         # The differentiable form (cfg5 geometry: 64^3, 16x16 array, 8 plane waves, FP32,
         # Re and Im lanes): forward, adjoint (channel-data gradient) and dL/dc;
-        # also the adjoint of the complex baseband form (the two lanes as one
-        # (I, Q) pair demodulated at 7.5 MHz).
+        # also the adjoint and dL/dc of the complex baseband form (the two
+        # lanes as one (I, Q) pair demodulated at 7.5 MHz).
         g5 = synth.cfg5()
         p5 = das.Plan(g5, max_batch=2, storage="f32")
         p5q = das.Plan(g5, max_batch=2, storage="f32")
@@ -394,7 +394,8 @@ def main():
         for name, fn in (("forward_ms", lambda: p5.forward_ws(ws5, 2, x5)),
                          ("adjoint_ms", lambda: das.das_adjoint(p5.handle, gx, 2, gy)),
                          ("adjoint_iq_ms", lambda: das.das_adjoint(p5q.handle, gx, 2, gyq)),
-                         ("grad_c_ms", lambda: p5.grad_sound_speed(y5, gx))):
+                         ("grad_c_ms", lambda: p5.grad_sound_speed(y5, gx)),
+                         ("grad_c_iq_ms", lambda: p5q.grad_sound_speed(y5, gx))):
             fn()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
@@ -408,7 +409,8 @@ def main():
                                             workload="64^3 voxels x 256 elements x 8 plane waves",
                                             data="random N(0,1) channel data and upstream gradient")
         log(f"cfg5 forward {timings['forward_ms']:.3f} ms, adjoint {timings['adjoint_ms']:.3f} ms, "
-            f"IQ adjoint {timings['adjoint_iq_ms']:.3f} ms, dL/dc {timings['grad_c_ms']:.3f} ms")
+            f"IQ adjoint {timings['adjoint_iq_ms']:.3f} ms, dL/dc {timings['grad_c_ms']:.3f} ms, "
+            f"IQ dL/dc {timings['grad_c_iq_ms']:.3f} ms")
         del y5, gx, ws5, x5, gy, gyq, dc
         p5.close()
         p5q.close()

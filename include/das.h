@@ -144,8 +144,9 @@ das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
  * FP8 storage (Alg. 3's complex W: the cosine and sine parts of the weights
  * contracted with the same sample fragments; COLUMN or SLAB launch), with an
  * even batch (DAS_ERR_UNSUPPORTED / DAS_ERR_INVALID_ARG otherwise).
- * das_adjoint of an IQ plan is the transpose of that map (even batch);
- * das_grad_sound_speed and das_forward_batched refuse IQ plans.
+ * das_adjoint and das_grad_sound_speed of an IQ plan are the transpose and
+ * the sound-speed derivative of that map (even batch); das_forward_batched
+ * refuses IQ plans.
  * enable = 0 restores real data. */
 das_status das_plan_set_iq(das_plan p, int32_t enable, double fc);
 /* Launch form of the MFMA algorithm (Sec. 3.4, Alg. 3); Sec. 3.2 says tile
@@ -242,6 +243,10 @@ das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, vo
  * Eq. (1) (grid, t0 and weights do not depend on c0):
  * dL/dc = sum_{b,n} gx[b][n] dx[b][n]/dc, with dx/dc = sum_{q,m} w (s(k+1)-s(k)) df/dc,
  * df/dc = -fs (D_tx + D_rx)/c^2 (right-hand slope at integer f).
+ * IQ plans (even batch; pairs (2b, 2b+1) = (I, Q) in y and gx): the phase
+ * exp(i 2 pi fc tau) turns with c too, dx/dc = sum w exp(i 2 pi fc tau)
+ * ((s(k+1)-s(k)) + i 2 pi (fc/fs) s_interp) df/dc, and
+ * dL/dc = sum gx[2b] Re(dx/dc) + gx[2b+1] Im(dx/dc).
  * y: device [batch][Q][M][K] f32 (caller layout); gx: device [batch][N] f32;
  * dLdc: device scalar f32, overwritten. */
 das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int32_t batch,

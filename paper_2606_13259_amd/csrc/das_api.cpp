@@ -620,11 +620,11 @@ das_status das_adjoint(das_plan p, const float* gx, int32_t batch, float* gy, vo
 das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int32_t batch,
                                 float* dLdc, void* stream) {
   if (das_status s = check_plan(p)) return s;
-  if (p->iq) return fail(DAS_ERR_UNSUPPORTED, "the gradient of the complex baseband form is not built");
   if (p->interp != DAS_INTERP_LINEAR)
     return fail(DAS_ERR_UNSUPPORTED, "the sound-speed gradient is built for linear interpolation only");
   if (!y || !gx || !dLdc) return fail(DAS_ERR_INVALID_ARG, "y, gx or dLdc is NULL");
   if (das_status s = check_batch(p, batch)) return s;
+  if (p->iq && batch % 2) return fail(DAS_ERR_INVALID_ARG, "complex baseband needs an even batch");
   DeviceGuard dg(p->device);
   hipError_t e = launch_grad_c(make_geom(p), y, gx, batch, dLdc, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "das_grad_sound_speed launch");

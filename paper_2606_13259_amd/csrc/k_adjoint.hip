@@ -238,7 +238,13 @@ __global__ __launch_bounds__(NT) void adjoint_scatter(Geom g, TileShape ts, Wind
 // of a group of QG; elements whose receive cone misses the box's bounding
 // sphere are skipped by the whole wavefront (the weight would be zero on
 // every lane).
-template <int BT>
+// IQ: items (2c, 2c+1) are the (I, Q) records of complex item c (BT even);
+// each term also turns with the phase 2 pi fc tau, so
+//   dx/dc = w exp(i 2 pi fc tau) ((s(k+1) - s(k)) + i 2 pi (fc/fs) s_interp) df/dc
+// (dtau/dc = (df/dc)/fs), and the pair adds gI Re(dx/dc) + gQ Im(dx/dc).  The
+// phase is formed as in the forward kernels: transmit and element parts in
+// FP64 per box, the box-relative part in FP32, hardware sine and cosine.
+template <int BT, bool IQ>
 __global__ __launch_bounds__(256) void grad_c_gather(Geom g, const float* __restrict__ y,
                                                      const float* __restrict__ gx, int B,
                                                      float* __restrict__ out, int nbx, int nby,
@@ -270,20 +276,28 @@ __global__ __launch_bounds__(256) void grad_c_gather(Geom g, const float* __rest
     float gxv[BT];
 #pragma unroll
     for (int b = 0; b < BT; ++b) gxv[b] = (inside && b0 + b < B) ? gx[(size_t)(b0 + b) * N + n] : 0.f;
+    const float fcfs_f = (float)g.fcfs;
+    const float turn = 6.283185307179586f * fcfs_f;  // 2 pi fc / fs, radians per sample
     for (int q0 = 0; q0 < g.Q; q0 += QG) {
       const int qn = min(QG, g.Q - q0);
       float bq[QG], wq[QG];
+      float rq[IQ ? QG : 1];  // IQ: the transmit's phase term (revolutions)
       int ktx[QG];
 #pragma unroll
       for (int q = 0; q < QG; ++q) {
         bq[q] = 0.f;
         wq[q] = 0.f;
         ktx[q] = 0;
+        if constexpr (IQ) rq[q] = 0.f;
         if (q < qn) {
           const TxRef tr = make_tx_ref(g, q0 + q, px, py, pz);
           bq[q] = fmaf(delta_tx(tr, dx, dy, dz, dp2), fscf, tr.g);
           wq[q] = (g.w_tx && inside) ? g.w_tx[(size_t)(q0 + q) * N + n] : 1.f;
           ktx[q] = tr.ktx;
+          if constexpr (IQ) {
+            const double rv = g.fcfs * (double)tr.ktx + g.fct0;
+            rq[q] = (float)(rv - floor(rv));
+          }
         }
       }
       for (int m0 = 0; m0 < g.M; m0 += 64) {
@@ -308,6 +322,11 @@ __global__ __launch_bounds__(256) void grad_c_gather(Geom g, const float* __rest
           if (__ballot(w != 0.f) == 0ull) continue;
           const float a = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, h);
           const float* ym = y + (size_t)q0 * MK + (size_t)m * g.K;
+          float rm = 0.f;  // IQ: the element's phase term frac(fc/fs krx)
+          if constexpr (IQ) {
+            const double rv = g.fcfs * (double)krx;
+            rm = (float)(rv - floor(rv));
+          }
 #pragma unroll
           for (int q = 0; q < QG; ++q) {
             if (q >= qn) break;
@@ -319,13 +338,34 @@ __global__ __launch_bounds__(256) void grad_c_gather(Geom g, const float* __rest
             const float dfdc = -((float)kb + f + t0fs) * inv_c;
             const float c = w * wq[q] * dfdc;
             const float* yq = ym + (size_t)q * MK;
+            if constexpr (IQ) {
+              const float al = f - fl;
+              const float rev = frac_f32(rq[IQ ? q : 0] + rm + fcfs_f * f);
+              const float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
 #pragma unroll
-            for (int b = 0; b < BT; ++b) {
-              if (b0 + b < B) {
-                const float* yb = yq + (size_t)(b0 + b) * QMK;
-                const float s1 = (k >= 0 && k < g.K) ? yb[k] : 0.f;
-                const float s2 = (k + 1 >= 0 && k + 1 < g.K) ? yb[k + 1] : 0.f;
-                total = fmaf(gxv[b] * c, s2 - s1, total);
+              for (int b = 0; b < BT; b += 2) {
+                if (b0 + b < B) {  // B even: the Q item b + 1 exists too
+                  const float* yi = yq + (size_t)(b0 + b) * QMK;
+                  const float* yqq = yi + QMK;
+                  const bool in1 = k >= 0 && k < g.K, in2 = k + 1 >= 0 && k + 1 < g.K;
+                  const float i1 = in1 ? yi[k] : 0.f, i2 = in2 ? yi[k + 1] : 0.f;
+                  const float q1 = in1 ? yqq[k] : 0.f, q2 = in2 ? yqq[k + 1] : 0.f;
+                  const float di = i2 - i1, dq = q2 - q1;
+                  const float vi = fmaf(al, di, i1), vq = fmaf(al, dq, q1);
+                  const float zi = fmaf(-turn, vq, di), zq = fmaf(turn, vi, dq);
+                  const float ri = fmaf(cs, zi, -sn * zq), rqv = fmaf(sn, zi, cs * zq);
+                  total = fmaf(c, fmaf(gxv[b], ri, gxv[b + 1] * rqv), total);
+                }
+              }
+            } else {
+#pragma unroll
+              for (int b = 0; b < BT; ++b) {
+                if (b0 + b < B) {
+                  const float* yb = yq + (size_t)(b0 + b) * QMK;
+                  const float s1 = (k >= 0 && k < g.K) ? yb[k] : 0.f;
+                  const float s2 = (k + 1 >= 0 && k + 1 < g.K) ? yb[k + 1] : 0.f;
+                  total = fmaf(gxv[b] * c, s2 - s1, total);
+                }
               }
             }
           }
@@ -408,15 +448,22 @@ hipError_t launch_grad_c(const Geom& g, const float* y, const float* gx, int B, 
   const int nbx = (g.n[0] + 3) / 4, nby = (g.n[1] + 3) / 4, nbz = (g.n[2] + 3) / 4;
   const int nblocks = nbx * nby * nbz;
   const float inv_c = (float)(1.0 / g.c);
-  if (B >= 4) {
-    hipLaunchKernelGGL(grad_c_gather<4>, dim3((nblocks + 3) / 4, (B + 3) / 4), dim3(256), 0, st, g,
-                       y, gx, B, dLdc, nbx, nby, nblocks, inv_c);
+  if (g.iq) {  // B even: pairs never straddle a block (BT even)
+    if (B >= 4)
+      hipLaunchKernelGGL((grad_c_gather<4, true>), dim3((nblocks + 3) / 4, (B + 3) / 4), dim3(256), 0,
+                         st, g, y, gx, B, dLdc, nbx, nby, nblocks, inv_c);
+    else
+      hipLaunchKernelGGL((grad_c_gather<2, true>), dim3((nblocks + 3) / 4, (B + 1) / 2), dim3(256), 0,
+                         st, g, y, gx, B, dLdc, nbx, nby, nblocks, inv_c);
+  } else if (B >= 4) {
+    hipLaunchKernelGGL((grad_c_gather<4, false>), dim3((nblocks + 3) / 4, (B + 3) / 4), dim3(256), 0,
+                       st, g, y, gx, B, dLdc, nbx, nby, nblocks, inv_c);
   } else if (B >= 2) {
-    hipLaunchKernelGGL(grad_c_gather<2>, dim3((nblocks + 3) / 4, (B + 1) / 2), dim3(256), 0, st, g,
-                       y, gx, B, dLdc, nbx, nby, nblocks, inv_c);
+    hipLaunchKernelGGL((grad_c_gather<2, false>), dim3((nblocks + 3) / 4, (B + 1) / 2), dim3(256), 0,
+                       st, g, y, gx, B, dLdc, nbx, nby, nblocks, inv_c);
   } else {
-    hipLaunchKernelGGL(grad_c_gather<1>, dim3((nblocks + 3) / 4, B), dim3(256), 0, st, g, y, gx, B,
-                       dLdc, nbx, nby, nblocks, inv_c);
+    hipLaunchKernelGGL((grad_c_gather<1, false>), dim3((nblocks + 3) / 4, B), dim3(256), 0, st, g, y,
+                       gx, B, dLdc, nbx, nby, nblocks, inv_c);
   }
   return hipGetLastError();
 }

@@ -170,6 +170,33 @@ def test_iq_adjoint_dot_product(gpu):
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
+@pytest.mark.parametrize("geom", ["small", "cfg5_block"])
+def test_iq_grad_sound_speed_vs_oracle(gpu, geom):
+    """dL/dc of the complex baseband form (delay and phase both move with c)
+    against oracle.iq.grad_sound_speed_iq at the bar of the real form."""
+    from oracle.iq import grad_sound_speed_iq
+    das = _das()
+    g = _geometry() if geom == "small" else synth.sub_grid(synth.cfg5(), (24, 24, 20), (12, 10, 8))
+    rng = np.random.default_rng(46)
+    C = 2
+    y = rng.normal(size=(C, g.Q, g.M, g.K)) + 1j * rng.normal(size=(C, g.Q, g.M, g.K))
+    gx = rng.normal(size=(C, g.N)) + 1j * rng.normal(size=(C, g.N))
+    y, gx = y.astype(np.complex64), gx.astype(np.complex64)
+    ref = grad_sound_speed_iq(y, gx, g, 7.5e6)
+    yl = np.empty((2 * C,) + y.shape[1:], np.float32)
+    yl[0::2], yl[1::2] = y.real, y.imag
+    gl = np.empty((2 * C, g.N), np.float32)
+    gl[0::2], gl[1::2] = gx.real, gx.imag
+    plan = das.Plan(g, max_batch=2 * C, storage="f32")
+    plan.set_iq(7.5e6)
+    got = float(plan.grad_sound_speed(torch.from_numpy(yl).to(gpu), torch.from_numpy(gl).to(gpu)))
+    say(f"  IQ dL/dc gpu={got:.7e} oracle={ref:.7e}")
+    assert abs(got - ref) <= 1e-4 * abs(ref)
+    with pytest.raises(das.DasError) as e:
+        plan.grad_sound_speed(torch.from_numpy(yl[:3]).to(gpu), torch.from_numpy(gl[:3]).to(gpu))
+    assert e.value.status == das.DAS_ERR_INVALID_ARG
+
+
 # --- complex baseband in the MFMA locality form (Alg. 3 with complex W) ---
 # Bars: f16 / FP8 storage of the I and Q records against the oracle on the raw
 # complex data (the storage bars of the real forms), and the kernel alone
