@@ -631,34 +631,74 @@ __global__ __launch_bounds__(1024) void tri_orth(const double* __restrict__ lam,
   }
 }
 
-// 4. V = Q Y for the basis eigenvectors, one workgroup per eigenvector j:
+// 4. V = Q Y for the basis eigenvectors, one wavefront per eigenvector j:
 // the Householder reflectors H_{T-3} .. H_0 applied in turn (u_k read from
-// row k, tau from LDS).
-__global__ __launch_bounds__(256) void tri_back(const double* __restrict__ A,
-                                                const double* __restrict__ tau,
-                                                const double* __restrict__ Y,
-                                                const double* __restrict__ lam, int T, int k_lo,
-                                                int k_hi, int keep, double* __restrict__ V) {
-  __shared__ double y[kMaxT], ts[kMaxT], red[16];
-  const int j = blockIdx.x, tid = threadIdx.x;
+// row k, tau from LDS).  Each step is a dot product and an update over at
+// most T - 1 entries.  The vector stays in registers (entry c in lane c mod
+// 64), so a step is a few LDS reads of u_k, FMAs and one shuffle reduction;
+// the rows are staged in LDS a chunk of 5120 / T rows at a time with all of
+// a chunk's loads in flight together.
+__global__ __launch_bounds__(64) void tri_back(const double* __restrict__ A,
+                                               const double* __restrict__ tau,
+                                               const double* __restrict__ Y,
+                                               const double* __restrict__ lam, int T, int k_lo,
+                                               int k_hi, int keep, double* __restrict__ V) {
+  constexpr int BUF = 5120;      // staged row entries (40 KiB)
+  constexpr int R = kMaxT / 64;  // vector entries per lane
+  __shared__ double ts[kMaxT], ub[BUF];
+  const int j = blockIdx.x, lane = threadIdx.x;
   if (!in_projection_basis(lam, T, j, k_lo, k_hi, keep)) return;  // uniform
-  for (int t = tid; t < T; t += blockDim.x) {
-    y[t] = Y[(size_t)t * T + j];
-    ts[t] = tau[t];
+  double y[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int c = lane + 64 * r;
+    y[r] = c < T ? Y[(size_t)c * T + j] : 0.0;
   }
-  __syncthreads();
-  for (int k = T - 3; k >= 0; --k) {
-    const double tk = ts[k];
-    if (tk == 0.0) continue;  // uniform
-    const int n = T - k - 1;
-    const double* uk = A + (size_t)k * T + (k + 1);
-    double part = 0.0;
-    for (int i = tid; i < n; i += blockDim.x) part += uk[i] * y[k + 1 + i];
-    const double s = tk * block_sum(part, red);
-    for (int i = tid; i < n; i += blockDim.x) y[k + 1 + i] -= s * uk[i];
+  for (int t = lane; t < T; t += 64) ts[t] = tau[t];
+  const int rows = BUF / T;  // >= 10 for T <= 512
+  for (int khi = T - 3; khi >= 0; khi -= rows) {
+    const int klo = max(khi - rows + 1, 0);
+    __syncthreads();  // the previous chunk's reads are done
+    // row k, entries k+1 .. T-1, to ub[(khi - k) T + column]: the chunk as
+    // one flat range, 32 loads per lane issued before their LDS stores
+    const int span = (khi - klo + 1) * T;
+    for (int base = 0; base < span; base += 64 * 32) {
+      double v[32];
+#pragma unroll
+      for (int m = 0; m < 32; ++m) {
+        const int idx = base + m * 64 + lane;
+        const int rr = idx / T, c = idx - rr * T, k = khi - rr;
+        v[m] = (idx < span && c > k) ? A[(size_t)k * T + c] : 0.0;
+      }
+#pragma unroll
+      for (int m = 0; m < 32; ++m) {
+        const int idx = base + m * 64 + lane;
+        if (idx < span) ub[idx] = v[m];
+      }
+    }
     __syncthreads();
+    for (int k = khi; k >= klo; --k) {
+      const double tk = ts[k];
+      if (tk == 0.0) continue;  // uniform
+      const double* u = ub + (size_t)(khi - k) * T;
+      double uk[R], part = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int c = lane + 64 * r;
+        uk[r] = (c > k && c < T) ? u[c] : 0.0;  // u_k is zero at and above k
+        part = fma(uk[r], y[r], part);
+      }
+      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+      const double sc = tk * part;
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[r] = fma(-sc, uk[r], y[r]);
+    }
   }
-  for (int t = tid; t < T; t += blockDim.x) V[(size_t)t * T + j] = y[t];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int c = lane + 64 * r;
+    if (c < T) V[(size_t)c * T + j] = y[r];
+  }
 }
 
 // Rank the eigenvalues (descending, ties by index), write sigma = sqrt(lambda),
@@ -777,6 +817,93 @@ __global__ __launch_bounds__(256) void power_1pass(const float* __restrict__ x, 
     const double p = keep ? aa : fmax(ss[v] - aa, 0.0);
     pd[n0 + v] = (float)(p / T);
   }
+}
+
+// The same one-pass power for small bases (nb <= 4) with the frames split
+// over the four wavefronts of a workgroup: each wavefront sums a quarter of
+// the frames for the block's 256 voxels (four neighbouring voxels per lane,
+// one 16-byte load per frame), then the partial sums (FP64) are added in LDS
+// in two pairwise rounds.  Four times the wavefronts of the voxel-per-thread
+// form for the same ensemble: more loads in flight and a short tail.
+template <int NBMAX>
+__global__ __launch_bounds__(256) void power_split(const float* __restrict__ x, int T, long long N,
+                                                   const double* __restrict__ Bd, int nb, int keep,
+                                                   float* __restrict__ pd) {
+  constexpr int VPT = 4, NV = NBMAX + 1, R = VPT * NV;  // partial sums per lane
+  extern __shared__ double Bs64[];                       // [T nb] basis, then [2][R][64] partials
+  double* const red = Bs64 + ((T * nb + 1) & ~1);
+  for (int i = threadIdx.x; i < T * nb; i += blockDim.x) Bs64[i] = Bd[i];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long n0 = ((long long)blockIdx.x * 64 + lane) * VPT;
+  const bool full = n0 + VPT <= N && (N & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  double part[R];  // [v][0] = sum s^2, [v][1 + j] = sum s B_j
+#pragma unroll
+  for (int i = 0; i < R; ++i) part[i] = 0.0;
+  if (n0 < N) {
+    const int tb = T * wave / 4, te = T * (wave + 1) / 4;
+#pragma unroll 4
+    for (int t = tb; t < te; ++t) {
+      const float* row = x + (long long)t * N + n0;
+      float sv[VPT];
+      if (full) {
+        const f32x4 q = *reinterpret_cast<const f32x4*>(row);
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) sv[v] = q[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < VPT; ++v) sv[v] = n0 + v < N ? row[v] : 0.f;
+      }
+#pragma unroll
+      for (int v = 0; v < VPT; ++v) {
+        const double d = (double)sv[v];
+        part[v * NV] = fma(d, d, part[v * NV]);
+#pragma unroll
+        for (int j = 0; j < NBMAX; ++j)
+          if (j < nb) part[v * NV + 1 + j] = fma(d, Bs64[t * nb + j], part[v * NV + 1 + j]);
+      }
+    }
+  }
+  // waves 2, 3 hand their sums to waves 0, 1; then wave 1 to wave 0
+  // (every wave reaches every barrier)
+  if (wave >= 2) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) red[((wave - 2) * R + i) * 64 + lane] = part[i];
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) part[i] += red[(wave * R + i) * 64 + lane];
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) red[i * 64 + lane] = part[i];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) {
+    if (n0 + v >= N) break;
+    double aa = 0.0;
+#pragma unroll
+    for (int j = 0; j < NBMAX; ++j) {
+      const double aj = part[v * NV + 1 + j] + red[(v * NV + 1 + j) * 64 + lane];
+      aa = fma(aj, aj, aa);
+    }
+    const double ss = part[v * NV] + red[(v * NV) * 64 + lane];
+    const double p = keep ? aa : fmax(ss - aa, 0.0);
+    pd[n0 + v] = (float)(p / T);
+  }
+}
+
+hipError_t launch_power_split(const float* x, int T, long long N, const double* Bd, int nb, int keep,
+                              float* pd, hipStream_t st) {
+  constexpr int NBMAX = 4, R = 4 * (NBMAX + 1);
+  const size_t lds = sizeof(double) * ((size_t)((T * nb + 1) & ~1) + 2 * R * 64);
+  hipLaunchKernelGGL((power_split<NBMAX>), dim3((unsigned)((N + 255) / 256)), dim3(256), lds, st, x,
+                     T, N, Bd, nb, keep, pd);
+  return hipGetLastError();
 }
 
 template <int NBMAX, int VPT>
@@ -923,13 +1050,13 @@ hipError_t launch_clutter_filter(const float* x, int T, long long N, int k_lo, i
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(tri_orth, dim3(1), dim3(1024), 0, st, lam, T, k_lo, k_hi, keep, Y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(tri_back, dim3(T), dim3(256), 0, st, A, tau, Y, lam, T, k_lo, k_hi, keep, V);
+  hipLaunchKernelGGL(tri_back, dim3(T), dim3(64), 0, st, A, tau, Y, lam, T, k_lo, k_hi, keep, V);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(rank_basis, dim3(1), dim3(1024), 0, st, lam, V, T, k_lo, k_hi, keep, sv, Bm, Bd,
                      nb);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!xf && nb > 0 && nb <= 16 && sizeof(double) * (size_t)T * nb <= 48 * 1024) {
-    if (nb <= 4) return launch_power_1pass<4, 4>(x, T, N, Bd, nb, keep, pd, st);
+    if (nb <= 4) return launch_power_split(x, T, N, Bd, nb, keep, pd, st);
     if (nb <= 8) return launch_power_1pass<8, 1>(x, T, N, Bd, nb, keep, pd, st);
     return launch_power_1pass<16, 1>(x, T, N, Bd, nb, keep, pd, st);
   }
