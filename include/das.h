@@ -142,11 +142,12 @@ das_status das_plan_set_tx_weights(das_plan p, const float* w_tx);
  * tau = (D_tx + D_rx)/c, from the interpolated complex samples s.  Runs in the
  * windowed algorithm with f32 storage, or in the MFMA algorithm with f16 or
  * FP8 storage (Alg. 3's complex W: the cosine and sine parts of the weights
- * contracted with the same sample fragments; COLUMN or SLAB launch), with an
- * even batch (DAS_ERR_UNSUPPORTED / DAS_ERR_INVALID_ARG otherwise).
- * das_adjoint and das_grad_sound_speed of an IQ plan are the transpose and
- * the sound-speed derivative of that map (even batch); das_forward_batched
- * refuses IQ plans.
+ * contracted with the same sample fragments; COLUMN, SLAB or PERSISTENT
+ * launch, the FP8-operand forms taking the f16-operand COLUMN or SLAB
+ * launch), with an even batch (DAS_ERR_UNSUPPORTED / DAS_ERR_INVALID_ARG
+ * otherwise).  das_adjoint and das_grad_sound_speed of an IQ plan are the
+ * transpose and the sound-speed derivative of that map (even batch);
+ * das_forward_batched takes IQ plans in the MFMA algorithm.
  * enable = 0 restores real data. */
 das_status das_plan_set_iq(das_plan p, int32_t enable, double fc);
 /* Launch form of the MFMA algorithm (Sec. 3.4, Alg. 3); Sec. 3.2 says tile
@@ -261,7 +262,11 @@ das_status das_grad_sound_speed(das_plan p, const float* y, const float* gx, int
  * resident workgroups.  Requirements: 1 <= count <= 16; all plans on one
  * device with the same storage type and the same algorithm for their batch,
  * windowed (each plan with its own tile shape) or MFMA (DAS_ERR_UNSUPPORTED
- * otherwise).  Results equal those of das_forward on each plan bit for bit.
+ * otherwise).  Complex baseband (IQ) plans: all plans of the launch or none
+ * (DAS_ERR_UNSUPPORTED), MFMA algorithm with f16 or FP8 storage
+ * (DAS_ERR_UNSUPPORTED otherwise), even batches (DAS_ERR_INVALID_ARG).
+ * Results equal those of das_forward on each plan bit for bit (for IQ
+ * plans: das_forward with the PERSISTENT form).
  * MFMA launches schedule their items dynamically through one of the 64
  * sets of work counters owned by plans[0] (the sets are taken in turn, so at
  * most 64 MFMA launches led by one plan may execute at the same time on

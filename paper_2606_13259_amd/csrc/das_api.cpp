@@ -572,8 +572,10 @@ das_status das_forward(das_plan p, const void* ws, int32_t batch, float* x, void
                   "complex baseband runs in the windowed algorithm with f32 storage or the MFMA "
                   "algorithm with f16 or fp8 storage");
     if (mfma_ok) {
-      // column or slab launch (the persistent and FP8-operand forms are not built for IQ)
+      // persistent, column or slab launch (the FP8-operand forms are not built
+      // for IQ: they fall back to the f16-operand column or slab launch)
       const int f = p->mfma_form;
+      if (f == DAS_MFMA_PERSISTENT) return forward_batched_mfma(1, &p, &ws, &batch, &x, stream);
       e = launch_mfma_forward_iq(g, p->cfg.storage, ws, batch, x, f == DAS_MFMA_SLAB || f == DAS_MFMA_SLAB_FP8,
                                  st);
       if (e != hipSuccess) return hip_fail(e, "das_forward launch");
@@ -651,7 +653,7 @@ static das_status forward_batched_mfma(int32_t count, const das_plan* plans, con
   das_plan_s* lead = plans[0];
   unsigned* ctr = lead->d_ctr + (size_t)(lead->ctr_next.fetch_add(1u) % kCounterSets) *
                                     (mfma_batched_counter_bytes() / sizeof(unsigned));
-  e = launch_mfma_batched(a, ctr, lead->cfg.storage, cus,
+  e = launch_mfma_batched(a, ctr, lead->cfg.storage, lead->iq, cus,
                           static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "das_forward_batched launch");
   return DAS_OK;
@@ -670,8 +672,10 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
       return fail(DAS_ERR_INVALID_ARG, "all plans of a batched launch must be on one device");
     if (plans[i]->cfg.storage != plans[0]->cfg.storage)
       return fail(DAS_ERR_UNSUPPORTED, "all plans of a batched launch must share the storage type");
-    if (plans[i]->iq)
-      return fail(DAS_ERR_UNSUPPORTED, "complex baseband plans run through das_forward only");
+    if (plans[i]->iq != plans[0]->iq)
+      return fail(DAS_ERR_UNSUPPORTED, "a batched launch takes complex baseband plans only or none");
+    if (plans[i]->iq && batch[i] % 2)
+      return fail(DAS_ERR_INVALID_ARG, "complex baseband needs (I, Q) pairs: an even batch");
     if (plans[i]->interp != DAS_INTERP_LINEAR)
       return fail(DAS_ERR_UNSUPPORTED, "cubic-interpolation plans run through das_forward only");
   }
@@ -687,6 +691,9 @@ das_status das_forward_batched(int32_t count, const das_plan* plans, const void*
   }
   DeviceGuard dg(plans[0]->device);
   const int storage = plans[0]->cfg.storage;
+  if (plans[0]->iq && (algo0 != DAS_ALGO_MFMA || storage == DAS_STORE_BF16))
+    return fail(DAS_ERR_UNSUPPORTED,
+                "batched complex baseband launches run in the MFMA algorithm with f16 or fp8 storage");
   if (algo0 == DAS_ALGO_MFMA) return forward_batched_mfma(count, plans, ws, batch, x, stream);
   int bt = 4, qn = 1;
   bool wtx = false;

@@ -120,11 +120,12 @@ struct MfmaBatchedArgs {
 // Fills the derived fields (column counts, work-list ranges) of `a` from
 // g, ws, x, B, TW, Kc of each plan and launches the persistent MFMA kernel,
 // which schedules its items through the device counters `ctr`
-// (mfma_batched_counter_bytes(), zeroed on `st` before the launch).
+// (mfma_batched_counter_bytes(), zeroed on `st` before the launch).  iq: every
+// plan is in complex baseband mode (f16 or FP8 storage).
 size_t mfma_batched_counter_bytes();
 // Whether a single-plan forward should use the persistent kernel.
 bool mfma_prefers_persistent(int storage, int B);
-hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, int cus,
+hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, bool iq, int cus,
                                hipStream_t st);
 size_t mfma_workspace_elems(const Geom& g, int B);  // samples (1, 2 bytes each)
 hipError_t launch_mfma_reorder(const Geom& g, int storage, const float* y, int b0, int nb, int btot,

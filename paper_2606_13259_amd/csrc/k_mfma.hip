@@ -378,8 +378,10 @@ __device__ inline int xcd_remap(int b, int nblocks) {
   return r * per + (k % X) * C + k / X;
 }
 
+// Complex baseband doubles the accumulators: its bodies get the register
+// budget of two wavefronts per SIMD (at three, some spilled).
 template <class T, class BX, int NB, int QN, bool WTX, class OP, bool IQ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 2 : 3))) void mfma_forward_stack(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 4 || IQ ? 2 : 3))) void mfma_forward_stack(
     Geom g, const T* __restrict__ ws, int B, int TW, int Kc, float* __restrict__ x, int ngx,
     int ngy, int ncols) {
   __shared__ __align__(16) float bq_lds[4 * QN * 64 * BX::ZS * (WTX ? 2 : 1)];
@@ -409,8 +411,8 @@ __global__ void zero_counters(unsigned* c) {
   if (threadIdx.x < kXcds) c[threadIdx.x] = 0u;
 }
 
-template <class T, int QN, bool WTX, int NBMAX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBMAX == 4 ? 2 : 3))) void mfma_forward_batched(
+template <class T, int QN, bool WTX, int NBMAX, bool IQ = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBMAX == 4 || IQ ? 2 : 3))) void mfma_forward_batched(
     MfmaBatchedArgs a, unsigned* __restrict__ ctr) {
   __shared__ __align__(16) float bq_lds[4 * QN * 64 * kStack * (WTX ? 2 : 1)];
   const long long total = a.first[a.count];
@@ -432,11 +434,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBMAX == 4 
     // each plan runs with its own batch tiles per wavefront (w.nb, uniform:
     // NBMAX or 1)
     if (w.nb == NBMAX)
-      stack_body<T, kBox, NBMAX, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc,
-                                            w.x, w.ngx, w.ngy, col, by, bq_lds);
+      stack_body<T, kBox, NBMAX, QN, WTX, Operand<T>, IQ>(w.g, static_cast<const T*>(w.ws), w.B,
+                                                          w.TW, w.Kc, w.x, w.ngx, w.ngy, col, by,
+                                                          bq_lds);
     else
-      stack_body<T, kBox, 1, QN, WTX>(w.g, static_cast<const T*>(w.ws), w.B, w.TW, w.Kc, w.x,
-                                        w.ngx, w.ngy, col, by, bq_lds);
+      stack_body<T, kBox, 1, QN, WTX, Operand<T>, IQ>(w.g, static_cast<const T*>(w.ws), w.B, w.TW,
+                                                      w.Kc, w.x, w.ngx, w.ngy, col, by, bq_lds);
   }
 }
 
@@ -570,9 +573,9 @@ hipError_t launch_box(const Geom& g, const void* ws, int B, float* x, bool slab,
   return slab ? launch_any<T, kSlab, OP>(g, ws, B, x, st) : launch_any<T, kBox, OP>(g, ws, B, x, st);
 }
 
-template <class T, int QN, bool WTX, int NBMAX>
+template <class T, int QN, bool WTX, int NBMAX, bool IQ>
 hipError_t batched_t(const MfmaBatchedArgs& a, unsigned* ctr, int cus, hipStream_t st) {
-  auto kern = mfma_forward_batched<T, QN, WTX, NBMAX>;
+  auto kern = mfma_forward_batched<T, QN, WTX, NBMAX, IQ>;
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0);
   if (e != hipSuccess) return e;
@@ -589,30 +592,31 @@ hipError_t batched_t(const MfmaBatchedArgs& a, unsigned* ctr, int cus, hipStream
   return hipGetLastError();
 }
 
-template <class T, int NBMAX>
+template <class T, int NBMAX, bool IQ = false>
 hipError_t batched_any(const MfmaBatchedArgs& a, unsigned* ctr, int qn, bool wtx, int cus,
                        hipStream_t st) {
   constexpr int QMAX = kStack >= 8 ? 4 : 8;
   if (qn == 1)
-    return wtx ? batched_t<T, 1, true, NBMAX>(a, ctr, cus, st)
-               : batched_t<T, 1, false, NBMAX>(a, ctr, cus, st);
+    return wtx ? batched_t<T, 1, true, NBMAX, IQ>(a, ctr, cus, st)
+               : batched_t<T, 1, false, NBMAX, IQ>(a, ctr, cus, st);
   if (qn <= 4)
-    return wtx ? batched_t<T, 4, true, NBMAX>(a, ctr, cus, st)
-               : batched_t<T, 4, false, NBMAX>(a, ctr, cus, st);
-  return wtx ? batched_t<T, QMAX, true, NBMAX>(a, ctr, cus, st)
-             : batched_t<T, QMAX, false, NBMAX>(a, ctr, cus, st);
+    return wtx ? batched_t<T, 4, true, NBMAX, IQ>(a, ctr, cus, st)
+               : batched_t<T, 4, false, NBMAX, IQ>(a, ctr, cus, st);
+  return wtx ? batched_t<T, QMAX, true, NBMAX, IQ>(a, ctr, cus, st)
+             : batched_t<T, QMAX, false, NBMAX, IQ>(a, ctr, cus, st);
 }
 
 // Largest batch tiles per wavefront in a persistent launch.  FP8 fragments are
 // half the registers of 16-bit ones, so the four-tile body fits without spills
 // next to the one-tile body; the 16-bit types keep the two-tile body (and
 // three wavefronts per SIMD), which measured faster for them in this kernel.
-int batched_nbmax(int storage) { return storage == DAS_STORE_FP8_E4M3 ? 4 : 2; }
+// Complex baseband doubles the accumulators: two tiles for every type.
+int batched_nbmax(int storage, bool iq) { return storage == DAS_STORE_FP8_E4M3 && !iq ? 4 : 2; }
 
 // Batch tiles per wavefront of a plan in a persistent launch: the kernel's
 // NBMAX body or the one-tile body.
-int persistent_nb(int storage, int B) {
-  const int nbmax = batched_nbmax(storage), tiles = mfma_stack_tiles(B);
+int persistent_nb(int storage, int B, bool iq) {
+  const int nbmax = batched_nbmax(storage, iq), tiles = mfma_stack_tiles(B);
   return tiles >= nbmax ? nbmax : nbmax == 2 ? tiles : 1;
 }
 
@@ -634,11 +638,11 @@ size_t mfma_batched_counter_bytes() { return kXcds * sizeof(unsigned); }
 // types up to two tiles; for FP8 only with four tiles (its one-tile body in
 // the four-tile kernel runs at two wavefronts per SIMD instead of three).
 bool mfma_prefers_persistent(int storage, int B) {
-  const int nbmax = batched_nbmax(storage), tiles = mfma_stack_tiles(B);
+  const int nbmax = batched_nbmax(storage, false), tiles = mfma_stack_tiles(B);
   return nbmax == 2 ? tiles <= 2 : tiles == nbmax;
 }
 
-hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, int cus,
+hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, bool iq, int cus,
                                hipStream_t st) {
   int qn = 1;
   bool wtx = false;
@@ -652,9 +656,12 @@ hipError_t launch_mfma_batched(MfmaBatchedArgs& a, unsigned* ctr, int storage, i
     w.ngy = (w.g.n[1] + 4 * kBox::GY - 1) / (4 * kBox::GY);
     w.ngroups = w.ngx * w.ngy * ((w.g.n[2] + kBox::GZ - 1) / kBox::GZ);  // wavefront boxes
     w.nbx = 0;
-    w.nb = persistent_nb(storage, w.B);
+    w.nb = persistent_nb(storage, w.B, iq);
     a.first[i + 1] = a.first[i] + w.ngroups * (mfma_batch_pad(w.B) / (16 * w.nb));
   }
+  // complex baseband (every plan of the launch; f16 or FP8 storage)
+  if (iq && storage == DAS_STORE_F16) return batched_any<_Float16, 2, true>(a, ctr, qn, wtx, cus, st);
+  if (iq) return batched_any<uint8_t, 2, true>(a, ctr, qn, wtx, cus, st);
   if (storage == DAS_STORE_F16) return batched_any<_Float16, 2>(a, ctr, qn, wtx, cus, st);
   if (storage == DAS_STORE_FP8_E4M3) return batched_any<uint8_t, 4>(a, ctr, qn, wtx, cus, st);
   return batched_any<uint16_t, 2>(a, ctr, qn, wtx, cus, st);

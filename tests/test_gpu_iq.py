@@ -245,6 +245,76 @@ def test_iq_mfma_random_records(gpu, form, storage, C):
     _check_c(x[items], forward_iq(yr[items], g, 7.5e6), *MFMA_KERNEL, "  rounded data")
 
 
+@pytest.mark.parametrize("storage", ["f16", "fp8"])
+@pytest.mark.parametrize("C", [8, 17])
+def test_iq_mfma_persistent_form(gpu, storage, C):
+    """The persistent kernel's complex baseband body: the column launch (the
+    same wavefront boxes and batch tiles per wavefront) bit for bit, and the
+    oracle at the storage bars."""
+    from tests.gpu_util import lowp_bars
+    g = _geometry()
+    rng = np.random.default_rng(200 + C)
+    y = (rng.normal(size=(C, g.Q, g.M, g.K)) + 1j * rng.normal(size=(C, g.Q, g.M, g.K))).astype(np.complex64)
+    say(f"IQ mfma persistent {storage}, {C} complex items")
+    x, _ = _run_mfma(g, y, 7.5e6, gpu, storage, "persistent")
+    xc, _ = _run_mfma(g, y, 7.5e6, gpu, storage, "column")
+    assert np.array_equal(x, xc), "persistent IQ launch differs from the column launch"
+    items = sorted({0, C - 1})
+    _check_c(x[items], forward_iq(y[items], g, 7.5e6), *lowp_bars(storage), "persistent")
+
+
+def test_iq_mfma_batched_launch(gpu):
+    """One persistent launch over two complex baseband plans (different grids,
+    arrays, transmit counts and batch sizes) equals separate persistent
+    launches bit for bit and the oracle within the f16 bars; a launch that
+    mixes complex and real plans, an odd complex batch and windowed complex
+    plans are refused."""
+    from tests.gpu_util import lowp_bars
+    das = _das()
+    geoms = [_geometry(), synth.sub_grid(synth.cfg5(), (20, 24, 10), (9, 8, 12))]
+    counts = [8, 9]
+    plans, wss, xs, ys = [], [], [], []
+    for i, (g, C) in enumerate(zip(geoms, counts)):
+        rng = np.random.default_rng(300 + i)
+        y = (rng.normal(size=(C, g.Q, g.M, g.K)) + 1j * rng.normal(size=(C, g.Q, g.M, g.K))).astype(np.complex64)
+        lanes = np.empty((2 * C,) + y.shape[1:], np.float32)
+        lanes[0::2], lanes[1::2] = y.real, y.imag
+        p = das.Plan(g, max_batch=2 * C, storage="f16", algo="mfma")
+        p.set_iq(7.5e6)
+        wss.append(p.prepare(torch.from_numpy(lanes).to(gpu)))
+        plans.append(p)
+        xs.append(torch.full((2 * C, p.N), float("nan"), device=gpu))
+        ys.append(y)
+    batches = [2 * C for C in counts]
+    das.das_forward_batched([p.handle for p in plans], wss, batches, xs)
+    for p, ws, x, y, g, B in zip(plans, wss, xs, ys, geoms, batches):
+        p.set_mfma_form("persistent")
+        assert torch.equal(x, p.forward_ws(ws, B)), "batched IQ launch differs from a separate launch"
+        xn = x.cpu().numpy().astype(np.float64)
+        xc = xn[0::2] + 1j * xn[1::2]
+        items = [0, B // 2 - 1]
+        _check_c(xc[items], forward_iq(y[items], g, 7.5e6), *lowp_bars("f16"), f"batched IQ {g.grid_dims}")
+    # a real plan cannot join a complex launch
+    g = geoms[0]
+    p_r = das.Plan(g, max_batch=16, storage="f16", algo="mfma")
+    ws_r = p_r.prepare(synth.random_channel_data(g, 16, seed=4).to(gpu))
+    with pytest.raises(das.DasError) as e:
+        das.das_forward_batched([plans[0].handle, p_r.handle], [wss[0], ws_r], [16, 16],
+                                [xs[0], torch.empty(16, p_r.N, device=gpu)])
+    assert e.value.status == das.DAS_ERR_UNSUPPORTED
+    # odd complex batch
+    with pytest.raises(das.DasError) as e:
+        das.das_forward_batched([plans[1].handle], [wss[1]], [17], [xs[1]])
+    assert e.value.status == das.DAS_ERR_INVALID_ARG
+    # windowed complex plans run through das_forward only
+    p_w = das.Plan(g, max_batch=2, storage="f32", algo="tiled")
+    p_w.set_iq(7.5e6)
+    ws_w = p_w.prepare(synth.random_channel_data(g, 2, seed=5).to(gpu))
+    with pytest.raises(das.DasError) as e:
+        das.das_forward_batched([p_w.handle], [ws_w], [2], [torch.empty(2, p_w.N, device=gpu)])
+    assert e.value.status == das.DAS_ERR_UNSUPPORTED
+
+
 def test_iq_mfma_refuses_bf16(gpu):
     das = _das()
     g = _geometry()
@@ -253,3 +323,40 @@ def test_iq_mfma_refuses_bf16(gpu):
     with pytest.raises(das.DasError) as e:
         p.forward(synth.random_channel_data(g, 16, seed=2).to(gpu))
     assert e.value.status == das.DAS_ERR_UNSUPPORTED
+
+
+def test_iq_cfg2_full_volume_sampled(gpu):
+    """The full 128^3 x 1024 x 16 volume in complex baseband, as the benchmark
+    forms run it: the simulated cfg2 frame made analytic and demodulated at
+    7.5 MHz, one complex frame through the windowed FP32 kernel, and the same
+    frame repeated 8 times through the MFMA form (f16 storage, column launch);
+    sampled voxels against the oracle computed one by one."""
+    from tests.gpu_util import lowp_bars, sample_voxels
+    das = _das()
+    g, y = cfg2_channel_data()
+    za = metrics.analytic_lanes(y)
+    tk = g.t0 + torch.arange(g.K, device=y.device, dtype=torch.float64) / g.fs
+    ph = -2.0 * np.pi * 7.5e6 * tk
+    lanes = torch.stack([za[0] * torch.cos(ph).float() - za[1] * torch.sin(ph).float(),
+                         za[0] * torch.sin(ph).float() + za[1] * torch.cos(ph).float()]).contiguous()
+    del za
+    idx = sample_voxels(g, 384, seed=11)
+    ln = lanes.cpu().numpy()
+    xo = forward_iq((ln[0] + 1j * ln[1])[None], g, 7.5e6, voxels=idx)[0]
+    ref = np.concatenate([xo.real, xo.imag])
+
+    plan = das.Plan(g, max_batch=2, storage="f32", algo="tiled")
+    plan.set_iq(7.5e6)
+    x = plan.forward(lanes).cpu().numpy().astype(np.float64)
+    check_close(np.concatenate([x[0][idx], x[1][idx]]), ref, REL_L2_F32, ABS_F32,
+                "IQ cfg2 full, windowed FP32, sampled voxels")
+    plan.close()
+
+    p16 = das.Plan(g, max_batch=16, storage="f16", algo="mfma")
+    p16.set_iq(7.5e6)
+    p16.set_mfma_form("column")
+    x8 = p16.forward(lanes.repeat(8, 1, 1, 1).contiguous()).cpu().numpy().astype(np.float64)
+    for c in (0, 7):
+        check_close(np.concatenate([x8[2 * c][idx], x8[2 * c + 1][idx]]), ref, *lowp_bars("f16"),
+                    f"IQ cfg2 full, MFMA f16 column, complex item {c}, sampled voxels")
+    p16.close()
