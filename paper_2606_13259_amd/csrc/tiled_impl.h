@@ -513,18 +513,28 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
       __syncthreads();
       float bq[QN];
       float wq[WTX ? QN : 1];
-      float rq[IQ ? QN : 1];
+      // complex baseband: the phase of a term splits into a transmit part
+      // (frac(fc/fs ktx + fc t0) + fc/fs bq) and an element part (frac(fc/fs
+      // krx) + fc/fs a); each is turned into a unit phasor once (per transmit
+      // of the group, per element) and a term's phasor is their product
+      float pcq[IQ ? QN : 1], psq[IQ ? QN : 1];
 #pragma unroll
       for (int q = 0; q < QN; ++q) {
         bq[q] = 0.f;
         if (WTX) wq[WTX ? q : 0] = 0.f;
-        if (IQ) rq[IQ ? q : 0] = 0.f;
+        if (IQ) pcq[IQ ? q : 0] = psq[IQ ? q : 0] = 0.f;
         if (q < qn) {
           const QInfo qi = qinfo[q];
-          if (IQ) rq[IQ ? q : 0] = __int_as_float(qi.rq);
           TxRef r;
           r.vx = qi.vx; r.vy = qi.vy; r.vz = qi.vz; r.vn = qi.vn; r.kind = qi.kind;
           bq[q] = fmaf(delta_tx(r, dx, dy, dz, dp2), fscf, qi.g);
+          if constexpr (IQ) {
+            // revolutions, reduced to [0, 1) before the hardware sine and
+            // cosine (which take revolutions)
+            const float rev = frac_f32(fmaf((float)g.fcfs, bq[q], __int_as_float(qi.rq)));
+            pcq[q] = __builtin_amdgcn_cosf(rev);
+            psq[q] = __builtin_amdgcn_sinf(rev);
+          }
           if (WTX)
             wq[WTX ? q : 0] = !inside ? 0.f : g.w_tx[(size_t)(txl ? txl[q0 + q] : q0 + q) * N + n];
         }
@@ -583,11 +593,14 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           const float w = rx_weight(g, mm & 0xffff, ax, ay, az);
           const float en = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(eN[e])));
           const float a = fmaf(delta_dist(ex, ey, ez, en, dx, dy, dz, dp2), fscf, eh);
-          // complex baseband: the element's phase term frac(fc/fs krx)
-          float rm = 0.f;
+          // complex baseband: the element's phasor, from frac(fc/fs krx)
+          // (FP64 before rounding: krx reaches thousands) + fc/fs a
+          float pcm = 1.f, psm = 0.f;
           if constexpr (IQ) {
             const double rv = g.fcfs * (double)__builtin_amdgcn_readfirstlane(eK[e]);
-            rm = (float)(rv - floor(rv));
+            const float rev = frac_f32(fmaf((float)g.fcfs, a, (float)(rv - floor(rv))));
+            pcm = __builtin_amdgcn_cosf(rev);
+            psm = __builtin_amdgcn_sinf(rev);
           }
           // tap index i = floor(f) + dint is in [1, 2 dint + 1] (window bound)
           constexpr int RS = row_stride(QN, BT);
@@ -602,12 +615,11 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
           auto taps = [&](auto qg_tag, int qa) {
             constexpr int QG = decltype(qg_tag)::value;
             constexpr int QC = CUBIC ? QG : 1;
-            float s1[QG][BT], s2[QG][BT], al[QG], fr[IQ ? QG : 1];
+            float s1[QG][BT], s2[QG][BT], al[QG];
             float s0[QC][BT], s3[QC][BT];
 #pragma unroll
             for (int r = 0; r < QG; ++r) {
               const float f = a + bq[qa + r];
-              if (IQ) fr[IQ ? r : 0] = f;
               al[r] = frac_f32(f);
               const float* pp = base + (__mul24(floor_i32(f), RS) + (qa + r) * BT);
 #pragma unroll
@@ -635,11 +647,10 @@ __device__ inline void tile_body(const Geom& g, const TileShape& ts, const Windo
                   acc[b] = fmaf(wt, fmaf(cm, s0[r][b], fmaf(c0, s1[r][b], fmaf(c1, s2[r][b], c2 * s3[r][b]))),
                                 acc[b]);
               } else if constexpr (IQ) {
-                // remodulate by exp(i 2 pi fc tau): revolutions fc/fs (ktx + krx
-                // + f) + fc t0, reduced to [0, 1) before the hardware sine and
-                // cosine (which take revolutions)
-                const float rev = frac_f32(rq[qa + r] + rm + (float)g.fcfs * fr[r]);
-                const float sn = __builtin_amdgcn_sinf(rev), cs = __builtin_amdgcn_cosf(rev);
+                // remodulate by exp(i 2 pi fc tau), the product of the
+                // transmit's and the element's phasors
+                const float cs = fmaf(pcq[qa + r], pcm, -psq[qa + r] * psm);
+                const float sn = fmaf(psq[qa + r], pcm, pcq[qa + r] * psm);
 #pragma unroll
                 for (int b = 0; b < BT; b += 2) {
                   const float vi = fmaf(al[r], s2[r][b], fmaf(-al[r], s1[r][b], s1[r][b]));

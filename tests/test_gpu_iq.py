@@ -2,8 +2,9 @@
 the FP64 oracle (oracle.iq.forward_iq, oracle.iq.adjoint_iq).  The phase
 rotation is formed from FP64 per-tile phase terms plus an FP32 tile-relative
 part (a few 1e-7 revolutions) and the hardware sine and cosine of the
-revolution count; the bar is the FP32 one (rel-L2 and elementwise 1e-5
-against the FP64 oracle)."""
+revolution count (in the windowed forward, of its transmit and element parts
+separately, whose phasors are multiplied); the bar is the FP32 one (rel-L2
+and elementwise 1e-5 against the FP64 oracle)."""
 import numpy as np
 import pytest
 import torch
