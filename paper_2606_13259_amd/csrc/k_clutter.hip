@@ -212,11 +212,6 @@ __global__ __launch_bounds__(256) void gram_full(const float* __restrict__ x, in
   }
 }
 
-// A(i, j) of the symmetric matrix kept in the upper triangle of a.
-__device__ inline double& up(double* a, int T, int i, int j) {
-  return i <= j ? a[(size_t)i * T + j] : a[(size_t)j * T + i];
-}
-
 constexpr int kMaxT = 512;
 
 // Block-wide FP64 sum over blockDim.x threads (a multiple of 64, at most
@@ -766,57 +761,34 @@ __global__ __launch_bounds__(256) void project_power(const float* __restrict__ x
 // the kept energy |a|^2 (keep form), and the removal form keeps
 // |s_n|^2 - |a|^2; both in FP64 with the FP64 basis, so the difference is
 // exact to far below the FP32 output even when the removed clutter is many
-// orders above the rest.  One read of the series; VPT neighbouring voxels per
-// thread (one 16-byte load per frame when VPT = 4 and the rows are aligned),
-// so that more bytes are in flight per thread.  NBMAX >= nb.
-template <int NBMAX, int VPT>
+// orders above the rest.  One read of the series, one voxel per thread (the
+// form for 5 to 16 basis vectors; smaller bases take power_split below).
+// NBMAX >= nb.
+template <int NBMAX>
 __global__ __launch_bounds__(256) void power_1pass(const float* __restrict__ x, int T, long long N,
                                                    const double* __restrict__ Bd, int nb, int keep,
                                                    float* __restrict__ pd) {
   extern __shared__ double Bs64[];
   for (int i = threadIdx.x; i < T * nb; i += blockDim.x) Bs64[i] = Bd[i];
   __syncthreads();
-  const long long n0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * VPT;
-  if (n0 >= N) return;
-  const bool full = VPT == 4 && n0 + VPT <= N && (N & 3) == 0 &&
-                    (reinterpret_cast<uintptr_t>(x) & 15) == 0;
-  double a[VPT][NBMAX], ss[VPT];
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  double a[NBMAX], ss = 0.0;
 #pragma unroll
-  for (int v = 0; v < VPT; ++v) {
-    ss[v] = 0.0;
-#pragma unroll
-    for (int j = 0; j < NBMAX; ++j) a[v][j] = 0.0;
-  }
+  for (int j = 0; j < NBMAX; ++j) a[j] = 0.0;
 #pragma unroll 4
   for (int t = 0; t < T; ++t) {
-    const float* row = x + (long long)t * N + n0;
-    float s[VPT];
-    if (full) {
-      const f32x4 q = *reinterpret_cast<const f32x4*>(row);
+    const double sv = (double)x[(long long)t * N + n];
+    ss = fma(sv, sv, ss);
 #pragma unroll
-      for (int v = 0; v < VPT; ++v) s[v] = q[v & 3];
-    } else {
-#pragma unroll
-      for (int v = 0; v < VPT; ++v) s[v] = n0 + v < N ? row[v] : 0.f;
-    }
-#pragma unroll
-    for (int v = 0; v < VPT; ++v) {
-      const double sv = (double)s[v];
-      ss[v] = fma(sv, sv, ss[v]);
-#pragma unroll
-      for (int j = 0; j < NBMAX; ++j)
-        if (j < nb) a[v][j] = fma(sv, Bs64[t * nb + j], a[v][j]);
-    }
+    for (int j = 0; j < NBMAX; ++j)
+      if (j < nb) a[j] = fma(sv, Bs64[t * nb + j], a[j]);
   }
+  double aa = 0.0;
 #pragma unroll
-  for (int v = 0; v < VPT; ++v) {
-    if (n0 + v >= N) break;
-    double aa = 0.0;
-#pragma unroll
-    for (int j = 0; j < NBMAX; ++j) aa = fma(a[v][j], a[v][j], aa);
-    const double p = keep ? aa : fmax(ss[v] - aa, 0.0);
-    pd[n0 + v] = (float)(p / T);
-  }
+  for (int j = 0; j < NBMAX; ++j) aa = fma(a[j], a[j], aa);
+  const double p = keep ? aa : fmax(ss - aa, 0.0);
+  pd[n] = (float)(p / T);
 }
 
 // The same one-pass power for small bases (nb <= 4) with the frames split
@@ -906,13 +878,12 @@ hipError_t launch_power_split(const float* x, int T, long long N, const double* 
   return hipGetLastError();
 }
 
-template <int NBMAX, int VPT>
+template <int NBMAX>
 hipError_t launch_power_1pass(const float* x, int T, long long N, const double* Bd, int nb, int keep,
                               float* pd, hipStream_t st) {
   const size_t lds = sizeof(double) * (size_t)T * nb;
-  const long long per = 256LL * VPT;
-  hipLaunchKernelGGL((power_1pass<NBMAX, VPT>), dim3((unsigned)((N + per - 1) / per)), dim3(256), lds,
-                     st, x, T, N, Bd, nb, keep, pd);
+  hipLaunchKernelGGL((power_1pass<NBMAX>), dim3((unsigned)((N + 255) / 256)), dim3(256), lds, st, x,
+                     T, N, Bd, nb, keep, pd);
   return hipGetLastError();
 }
 
@@ -1057,8 +1028,8 @@ hipError_t launch_clutter_filter(const float* x, int T, long long N, int k_lo, i
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!xf && nb > 0 && nb <= 16 && sizeof(double) * (size_t)T * nb <= 48 * 1024) {
     if (nb <= 4) return launch_power_split(x, T, N, Bd, nb, keep, pd, st);
-    if (nb <= 8) return launch_power_1pass<8, 1>(x, T, N, Bd, nb, keep, pd, st);
-    return launch_power_1pass<16, 1>(x, T, N, Bd, nb, keep, pd, st);
+    if (nb <= 8) return launch_power_1pass<8>(x, T, N, Bd, nb, keep, pd, st);
+    return launch_power_1pass<16>(x, T, N, Bd, nb, keep, pd, st);
   }
   if (nb == 0) {  // keep nothing or remove nothing
     return launch_project<1>(x, T, N, Bm, 0, keep, pd, xf, st);
